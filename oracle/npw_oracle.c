@@ -1,0 +1,461 @@
+/*
+ * npw_oracle.c -- plain, slow FP64 CPU oracle for the non-polynomial (multiquadric-RBF
+ * perturbed) WENO5 finite-volume scheme of J. Guo and J.-H. Jung, "Non-polynomial ENO and
+ * WENO finite volume methods for hyperbolic conservation laws" (arXiv:1602.00182).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product path may link, load or call this file:
+ * only the tests, the smoke check and the CPU-baseline leg of the benchmark use it.  It
+ * shares no code, header, table or constant with the HIP implementation.
+ *
+ * Everything is IEEE double precision, evaluated in the order written (build with
+ * -ffp-contract=off, no fast-math).  Each function names the passage of the paper it
+ * follows.  Where the paper is silent or garbled, the reading taken is stated at the
+ * function ("Reading: ...").
+ *
+ * Layout of a state array: component-major, u[c*nx + i] in 1D and u[(c*ny + j)*nx + i] in
+ * 2D, c = 0..ncomp-1.  Euler states are conservative: (rho, rho*u, E) in 1D and
+ * (rho, rho*u, rho*v, E) in 2D.
+ */
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include "npw_oracle.h"
+
+/* ------------------------------------------------------------------------------------ */
+/* Reconstruction coefficients, Table 3 (k = 3).                                          */
+/*                                                                                        */
+/* Row r (r = -1, 0, 1, 2) reconstructs the value at x_{i+1/2} from the three cell        */
+/* averages ubar_{i-r}, ubar_{i-r+1}, ubar_{i-r+2} as                                     */
+/*     v = sum_j (c_rj + eta * p_rj) * ubar_{i-r+j},   eta = eps^2 dx^2.                   */
+/* Left half of Table 3 gives c_rj (the eps -> 0 polynomial limit); the right half gives   */
+/* c_rj + eta p_rj.  Reading: the printed r = -1, j = 0 entry "6/11" is 11/6 (every        */
+/* polynomial row must sum to one, and 11/6 is the mirror of the r = 2, j = 2 entry).      */
+/* ------------------------------------------------------------------------------------ */
+static const double TAB_C[4][3] = {
+    /* r = -1 */ {11.0 / 6.0, -7.0 / 6.0, 1.0 / 3.0},
+    /* r =  0 */ {1.0 / 3.0, 5.0 / 6.0, -1.0 / 6.0},
+    /* r =  1 */ {-1.0 / 6.0, 5.0 / 6.0, 1.0 / 3.0},
+    /* r =  2 */ {1.0 / 3.0, -7.0 / 6.0, 11.0 / 6.0},
+};
+static const double TAB_P[4][3] = {
+    /* r = -1 */ {-9.0 / 2.0, 6.0, -3.0 / 2.0},
+    /* r =  0 */ {5.0 / 6.0, -2.0 / 3.0, -1.0 / 6.0},
+    /* r =  1 */ {-1.0 / 6.0, -2.0 / 3.0, 5.0 / 6.0},
+    /* r =  2 */ {-3.0 / 2.0, 6.0, -9.0 / 2.0},
+};
+
+void npo_table3(double c[12], double p[12]) {
+  for (int r = 0; r < 4; ++r)
+    for (int j = 0; j < 3; ++j) {
+      c[3 * r + j] = TAB_C[r][j];
+      p[3 * r + j] = TAB_P[r][j];
+    }
+}
+
+/* Value at x_{i+1/2} of table row r (r = -1..2) applied to (w0, w1, w2) =
+ * (ubar_{i-r}, ubar_{i-r+1}, ubar_{i-r+2}); the reconstruction form of Section 2. */
+double npo_row_value(int r, double w0, double w1, double w2, double eta) {
+  const double* c = TAB_C[r + 1];
+  const double* p = TAB_P[r + 1];
+  return (c[0] + eta * p[0]) * w0 + (c[1] + eta * p[1]) * w1 + (c[2] + eta * p[2]) * w2;
+}
+
+/* ------------------------------------------------------------------------------------ */
+/* Shape parameter eta = eps^2 dx^2 at the interface x_{i+1/2}, Table 3 caption (k = 3):   */
+/*     eta = (u_{i-1} - 3u_i + 3u_{i+1} - u_{i+2}) / (u_{i-1} - 15u_i + 15u_{i+1} - u_{i+2}  */
+/*           + eps_M).                                                                    */
+/* Reading: one eta per interface, from the four cells around it, shared by every row     */
+/* used at that interface.  eps_M is the "positive small number" of Section 3.2 that      */
+/* keeps the denominator away from zero; since the undivided difference in the            */
+/* denominator takes either sign, it is added with the sign of that difference (+ at 0).  */
+/* ------------------------------------------------------------------------------------ */
+double npo_eta(double um1, double u0, double up1, double up2, double eps_m) {
+  double num = um1 - 3.0 * u0 + 3.0 * up1 - up2;
+  double den = um1 - 15.0 * u0 + 15.0 * up1 - up2;
+  if (den >= 0.0)
+    den = den + eps_m;
+  else
+    den = den - eps_m;
+  return num / den;
+}
+
+/* ------------------------------------------------------------------------------------ */
+/* Monotone-polynomial test, Section 4, eqs. (root_value) and (adaptation).              */
+/* The quadratic through the three cell averages ubar_{j-1}, ubar_j, ubar_{j+1} (the       */
+/* derivative of the cubic interpolant of the primitive on x_{j-3/2}..x_{j+3/2}) has its   */
+/* extremum at                                                                            */
+/*     x_p / dx = (-2 u_{j-1} + 3 u_j - u_{j+1}) / (-u_{j-1} + 2 u_j - u_{j+1}),          */
+/* measured from x_{j-3/2}.  The window is "not monotone" when 0 < x_p/dx < 3.  Linear     */
+/* data (zero denominator) gives +-inf or NaN, which fails both strict inequalities, so    */
+/* linear windows are monotone, as they should be.                                        */
+/* Returns 1 when the window is not monotone (the shape parameter must vanish).           */
+/* ------------------------------------------------------------------------------------ */
+int npo_monotone_flag(double um1, double u0, double up1) {
+  double num = -2.0 * um1 + 3.0 * u0 - up1;
+  double den = -um1 + 2.0 * u0 - up1;
+  double xp = num / den;
+  return (xp > 0.0 && xp < 3.0) ? 1 : 0;
+}
+
+/* ------------------------------------------------------------------------------------ */
+/* Jiang-Shu smoothness indicators of the three substencils of cell i (Section 2 defers   */
+/* them to Shu's lecture notes).  u5 = (u_{i-2}, .., u_{i+2}); beta[r] belongs to the     */
+/* stencil S_r(i) = {i-r, .., i-r+2}.  They are the scaled integrals over I_i of the       */
+/* squared first and second derivatives of each stencil's quadratic.                      */
+/* ------------------------------------------------------------------------------------ */
+void npo_beta(const double u5[5], double beta[3]) {
+  double a = u5[0], b = u5[1], c = u5[2], d = u5[3], e = u5[4];
+  double t;
+  /* S_0 = {i, i+1, i+2} */
+  t = c - 2.0 * d + e;
+  beta[0] = 13.0 / 12.0 * t * t;
+  t = 3.0 * c - 4.0 * d + e;
+  beta[0] = beta[0] + 0.25 * t * t;
+  /* S_1 = {i-1, i, i+1} */
+  t = b - 2.0 * c + d;
+  beta[1] = 13.0 / 12.0 * t * t;
+  t = b - d;
+  beta[1] = beta[1] + 0.25 * t * t;
+  /* S_2 = {i-2, i-1, i} */
+  t = a - 2.0 * b + c;
+  beta[2] = 13.0 / 12.0 * t * t;
+  t = a - 4.0 * b + 3.0 * c;
+  beta[2] = beta[2] + 0.25 * t * t;
+}
+
+/* Nonlinear weights of eq. (weno_re): alpha_r = d_r / (eps + beta_r)^2, w_r = alpha_r /
+ * sum_s alpha_s. */
+static void weno_weights(const double d[3], const double beta[3], double eps, double w[3]) {
+  double a[3], s;
+  for (int r = 0; r < 3; ++r) a[r] = d[r] / ((eps + beta[r]) * (eps + beta[r]));
+  s = a[0] + a[1] + a[2];
+  for (int r = 0; r < 3; ++r) w[r] = a[r] / s;
+}
+
+/* Linear weights for k = 3.  Left-biased value v^-_{i+1/2}: d = (3/10, 3/5, 1/10) for
+ * r = 0, 1, 2.  Right-biased value v^+_{i-1/2}: the mirror, (1/10, 3/5, 3/10). */
+static const double D_MINUS[3] = {3.0 / 10.0, 3.0 / 5.0, 1.0 / 10.0};
+static const double D_PLUS[3] = {1.0 / 10.0, 3.0 / 5.0, 3.0 / 10.0};
+
+/* v^-_{i+1/2} of cell i, eq. (weno_re): convex combination of the three substencil values
+ * of Table 3 rows r = 0, 1, 2 at x_{i+1/2}, each perturbed with the interface's eta. */
+double npo_recon_minus(const double u5[5], double eta_right, double eps) {
+  double beta[3], w[3], q[3];
+  npo_beta(u5, beta);
+  weno_weights(D_MINUS, beta, eps, w);
+  for (int r = 0; r < 3; ++r) q[r] = npo_row_value(r, u5[2 - r], u5[3 - r], u5[4 - r], eta_right);
+  return w[0] * q[0] + w[1] * q[1] + w[2] * q[2];
+}
+
+/* v^+_{i-1/2} of cell i: the same construction at the left edge of I_i.  The substencil
+ * S_r(i) value at x_{i-1/2} is table row r - 1 at the interface x_{i-1/2} (the stencil
+ * {i-r..i-r+2} seen from the cell to the left of that interface), perturbed with the eta of
+ * x_{i-1/2}; the smoothness indicators are those of cell i. */
+double npo_recon_plus(const double u5[5], double eta_left, double eps) {
+  double beta[3], w[3], q[3];
+  npo_beta(u5, beta);
+  weno_weights(D_PLUS, beta, eps, w);
+  for (int r = 0; r < 3; ++r) q[r] = npo_row_value(r - 1, u5[2 - r], u5[3 - r], u5[4 - r], eta_left);
+  return w[0] * q[0] + w[1] * q[1] + w[2] * q[2];
+}
+
+/* ------------------------------------------------------------------------------------ */
+/* Physical fluxes and spectral radii (Section 5.1; Example 4 for Euler).                 */
+/* ------------------------------------------------------------------------------------ */
+static void phys_flux(const npo_problem* pb, int dir, const double* U, double* F) {
+  if (pb->flux == NPO_ADVECTION) {
+    F[0] = (dir == 0 ? pb->speed_x : pb->speed_y) * U[0];
+  } else if (pb->flux == NPO_BURGERS) {
+    F[0] = 0.5 * U[0] * U[0];
+  } else if (pb->ncomp == 3) { /* 1D Euler, Example 4 */
+    double rho = U[0], m = U[1], E = U[2];
+    double u = m / rho;
+    double p = (pb->gamma - 1.0) * (E - 0.5 * rho * u * u);
+    F[0] = m;
+    F[1] = m * u + p;
+    F[2] = (E + p) * u;
+  } else { /* 2D Euler: dir 0 is the x flux f, dir 1 the y flux g */
+    double rho = U[0], mx = U[1], my = U[2], E = U[3];
+    double u = mx / rho, v = my / rho;
+    double p = (pb->gamma - 1.0) * (E - 0.5 * rho * (u * u + v * v));
+    if (dir == 0) {
+      F[0] = mx;
+      F[1] = mx * u + p;
+      F[2] = my * u;
+      F[3] = (E + p) * u;
+    } else {
+      F[0] = my;
+      F[1] = mx * v;
+      F[2] = my * v + p;
+      F[3] = (E + p) * v;
+    }
+  }
+}
+
+/* Spectral radius of dF/dU in direction dir at a cell-average state.  Returns -1 for a
+ * non-physical Euler state (rho <= 0 or p <= 0), NaN propagates. */
+static double spectral_radius(const npo_problem* pb, int dir, const double* U) {
+  if (pb->flux == NPO_ADVECTION) return fabs(dir == 0 ? pb->speed_x : pb->speed_y);
+  if (pb->flux == NPO_BURGERS) return fabs(U[0]);
+  if (pb->ncomp == 3) {
+    double rho = U[0], u = U[1] / rho;
+    double p = (pb->gamma - 1.0) * (U[2] - 0.5 * rho * u * u);
+    if (!(rho > 0.0) || !(p > 0.0)) return -1.0;
+    return fabs(u) + sqrt(pb->gamma * p / rho);
+  } else {
+    double rho = U[0], u = U[1] / rho, v = U[2] / rho;
+    double p = (pb->gamma - 1.0) * (U[3] - 0.5 * rho * (u * u + v * v));
+    if (!(rho > 0.0) || !(p > 0.0)) return -1.0;
+    return fabs(dir == 0 ? u : v) + sqrt(pb->gamma * p / rho);
+  }
+}
+
+/* Global Lax-Friedrichs flux h(a, b) = 1/2 [f(a) + f(b) - alpha (b - a)], Section 5.1,
+ * component by component on vector states. */
+static void lf_flux(const npo_problem* pb, int dir, const double* a, const double* b, double alpha,
+                    double* h) {
+  double fa[4], fb[4];
+  phys_flux(pb, dir, a, fa);
+  phys_flux(pb, dir, b, fb);
+  for (int c = 0; c < pb->ncomp; ++c) h[c] = 0.5 * (fa[c] + fb[c] - alpha * (b[c] - a[c]));
+}
+
+/* Ghost index: periodic wrap or transmissive (copy of the edge cell).  Reading: the paper
+ * gives no boundary treatment beyond "appropriate boundary conditions" (Section 1). */
+static long ghost(long i, long n, int bc) {
+  if (bc == NPO_PERIODIC) {
+    long m = i % n;
+    return m < 0 ? m + n : m;
+  }
+  if (i < 0) return 0;
+  if (i >= n) return n - 1;
+  return i;
+}
+
+/* ------------------------------------------------------------------------------------ */
+/* Interface states along one grid line of n cells: for every interface x_{i+1/2},        */
+/* i = -1..n-1 (stored at index i+1), compute eta, the switch, v^- (from cell i) and v^+   */
+/* (from cell i+1).  line[] holds the n cell averages of one component; ghosts follow bc. */
+/* ------------------------------------------------------------------------------------ */
+void npo_line_states(const npo_problem* pb, const double* line, long n, double* vminus,
+                     double* vplus, double* eta_out, int* flag_out) {
+  /* G(k) = cell average of cell k (ghosts included), k = -3..n+2 */
+#define G(k) line[ghost((k), n, pb->bc)]
+  for (long i = -1; i <= n - 1; ++i) {
+    /* interface x_{i+1/2}, stored at index i+1 */
+    double eta = 0.0;
+    int flag = 0;
+    if (pb->recon == NPO_RBF_WENO5) {
+      eta = npo_eta(G(i - 1), G(i), G(i + 1), G(i + 2), pb->eps_m);
+      if (pb->switch_mode == NPO_SWITCH_MONOTONE) {
+        /* Reading (k = 3 switch): the interface's eta vanishes when either 3-cell window
+         * centred on a cell adjacent to it is not monotone, each window tested with the
+         * Section 4 criterion. */
+        flag = npo_monotone_flag(G(i - 1), G(i), G(i + 1)) || npo_monotone_flag(G(i), G(i + 1), G(i + 2));
+        if (flag) eta = 0.0;
+      }
+    }
+    double uL[5], uR[5];
+    for (int k = 0; k < 5; ++k) {
+      uL[k] = G(i - 2 + k); /* cells i-2..i+2: v^- of cell i */
+      uR[k] = G(i - 1 + k); /* cells i-1..i+3: v^+ of cell i+1 */
+    }
+    vminus[i + 1] = npo_recon_minus(uL, eta, pb->eps_weno);
+    vplus[i + 1] = npo_recon_plus(uR, eta, pb->eps_weno);
+    if (eta_out) eta_out[i + 1] = eta;
+    if (flag_out) flag_out[i + 1] = flag;
+  }
+#undef G
+}
+
+static int validate(const npo_problem* pb) {
+  if (!pb) return NPO_EINVAL;
+  if (pb->dim != 1 && pb->dim != 2) return NPO_EINVAL;
+  if (pb->nx < 1 || (pb->dim == 2 && pb->ny < 1)) return NPO_EINVAL;
+  if (pb->flux == NPO_EULER) {
+    if ((pb->dim == 1 && pb->ncomp != 3) || (pb->dim == 2 && pb->ncomp != 4)) return NPO_EINVAL;
+    if (!(pb->gamma > 1.0)) return NPO_EINVAL;
+  } else if (pb->flux == NPO_ADVECTION || pb->flux == NPO_BURGERS) {
+    if (pb->ncomp != 1) return NPO_EINVAL;
+  } else {
+    return NPO_EINVAL;
+  }
+  if (pb->bc != NPO_PERIODIC && pb->bc != NPO_TRANSMISSIVE) return NPO_EINVAL;
+  if (!(pb->x1 > pb->x0) || (pb->dim == 2 && !(pb->y1 > pb->y0))) return NPO_EINVAL;
+  if (!(pb->cfl > 0.0) || !(pb->eps_weno > 0.0) || !(pb->eps_m > 0.0)) return NPO_EINVAL;
+  if (pb->recon != NPO_RBF_WENO5 && pb->recon != NPO_WENO5_JS) return NPO_EINVAL;
+  if (pb->switch_mode != NPO_SWITCH_MONOTONE && pb->switch_mode != NPO_SWITCH_OFF) return NPO_EINVAL;
+  return NPO_OK;
+}
+
+/* Global Lax-Friedrichs alpha per direction: max over cells of the spectral radius of the
+ * cell-average state (Section 5.1, "alpha = max |df/du|"; reading: the max is taken over
+ * the cell averages of the current stage). */
+int npo_alpha(const npo_problem* pb, const double* u, double alpha[2]) {
+  int rc = validate(pb);
+  if (rc) return rc;
+  long ny = pb->dim == 2 ? pb->ny : 1, ncell = pb->nx * ny;
+  alpha[0] = 0.0;
+  alpha[1] = 0.0;
+  for (long k = 0; k < ncell; ++k) {
+    double U[4];
+    for (int c = 0; c < pb->ncomp; ++c) {
+      U[c] = u[c * ncell + k];
+      if (!isfinite(U[c])) return NPO_ENONFINITE;
+    }
+    for (int dir = 0; dir < pb->dim; ++dir) {
+      double s = spectral_radius(pb, dir, U);
+      if (s < 0.0) return NPO_ENONPHYSICAL;
+      if (s > alpha[dir]) alpha[dir] = s;
+    }
+  }
+  return NPO_OK;
+}
+
+/* ------------------------------------------------------------------------------------ */
+/* Semi-discrete right-hand side, eq. (PDE1) (1D) and eq. (2DIntegral) with one midpoint  */
+/* quadrature point per face (2D, dimension by dimension):                               */
+/*     L_i = -(F_{i+1/2} - F_{i-1/2}) / dx   [- (G_{j+1/2} - G_{j-1/2}) / dy].            */
+/* ------------------------------------------------------------------------------------ */
+int npo_rhs(const npo_problem* pb, const double* u, double* L, double alpha_out[2]) {
+  double alpha[2];
+  int rc = npo_alpha(pb, u, alpha);
+  if (rc) return rc;
+  if (alpha_out) {
+    alpha_out[0] = alpha[0];
+    alpha_out[1] = alpha[1];
+  }
+  const int m = pb->ncomp;
+  const long nx = pb->nx, ny = pb->dim == 2 ? pb->ny : 1, ncell = nx * ny;
+  const double dx = (pb->x1 - pb->x0) / (double)nx;
+  const double dy = pb->dim == 2 ? (pb->y1 - pb->y0) / (double)ny : 1.0;
+  long nmax = nx > ny ? nx : ny;
+  double* line = (double*)malloc(sizeof(double) * (size_t)nmax);
+  double* vm = (double*)malloc(sizeof(double) * (size_t)(nmax + 1) * (size_t)m);
+  double* vp = (double*)malloc(sizeof(double) * (size_t)(nmax + 1) * (size_t)m);
+  double* F = (double*)malloc(sizeof(double) * (size_t)(nmax + 1) * (size_t)m);
+
+  /* x sweep: every row j */
+  for (long j = 0; j < ny; ++j) {
+    for (int c = 0; c < m; ++c) {
+      for (long i = 0; i < nx; ++i) line[i] = u[c * ncell + j * nx + i];
+      npo_line_states(pb, line, nx, vm + (size_t)c * (nx + 1), vp + (size_t)c * (nx + 1), NULL, NULL);
+    }
+    for (long f = 0; f <= nx; ++f) {
+      double a[4], b[4], h[4];
+      for (int c = 0; c < m; ++c) {
+        a[c] = vm[(size_t)c * (nx + 1) + f];
+        b[c] = vp[(size_t)c * (nx + 1) + f];
+      }
+      lf_flux(pb, 0, a, b, alpha[0], h);
+      for (int c = 0; c < m; ++c) F[(size_t)c * (nx + 1) + f] = h[c];
+    }
+    for (int c = 0; c < m; ++c)
+      for (long i = 0; i < nx; ++i)
+        L[c * ncell + j * nx + i] = -(F[(size_t)c * (nx + 1) + i + 1] - F[(size_t)c * (nx + 1) + i]) / dx;
+  }
+  if (pb->dim == 2) {
+    /* y sweep: every column i, added to the x contribution */
+    for (long i = 0; i < nx; ++i) {
+      for (int c = 0; c < m; ++c) {
+        for (long j = 0; j < ny; ++j) line[j] = u[c * ncell + j * nx + i];
+        npo_line_states(pb, line, ny, vm + (size_t)c * (ny + 1), vp + (size_t)c * (ny + 1), NULL, NULL);
+      }
+      for (long f = 0; f <= ny; ++f) {
+        double a[4], b[4], h[4];
+        for (int c = 0; c < m; ++c) {
+          a[c] = vm[(size_t)c * (ny + 1) + f];
+          b[c] = vp[(size_t)c * (ny + 1) + f];
+        }
+        lf_flux(pb, 1, a, b, alpha[1], h);
+        for (int c = 0; c < m; ++c) F[(size_t)c * (ny + 1) + f] = h[c];
+      }
+      for (int c = 0; c < m; ++c)
+        for (long j = 0; j < ny; ++j)
+          L[c * ncell + j * nx + i] =
+              L[c * ncell + j * nx + i] - (F[(size_t)c * (ny + 1) + j + 1] - F[(size_t)c * (ny + 1) + j]) / dy;
+    }
+  }
+  free(line);
+  free(vm);
+  free(vp);
+  free(F);
+  return NPO_OK;
+}
+
+/* Time step: dt = CFL dx / alpha in 1D, CFL / (alpha_x/dx + alpha_y/dy) in 2D, clipped to
+ * the remaining time; a positive dt_fixed replaces the CFL rule (used to reproduce the
+ * accuracy tables without time error). */
+static double time_step(const npo_problem* pb, const double alpha[2], double remaining) {
+  double dt;
+  const double dx = (pb->x1 - pb->x0) / (double)pb->nx;
+  if (pb->dt_fixed > 0.0) {
+    dt = pb->dt_fixed;
+  } else if (pb->dim == 1) {
+    dt = pb->cfl * dx / alpha[0];
+  } else {
+    const double dy = (pb->y1 - pb->y0) / (double)pb->ny;
+    dt = pb->cfl / (alpha[0] / dx + alpha[1] / dy);
+  }
+  if (dt > remaining) dt = remaining;
+  return dt;
+}
+
+static int finite_and_physical(const npo_problem* pb, const double* u) {
+  double alpha[2];
+  return npo_alpha(pb, u, alpha);
+}
+
+/* ------------------------------------------------------------------------------------ */
+/* One step of the third-order TVD (SSP) Runge-Kutta method of Shu and Osher, which the   */
+/* paper uses for time integration (Section 5.1):                                         */
+/*   u1 = un + dt L(un);  u2 = 3/4 un + 1/4 (u1 + dt L(u1));                              */
+/*   un+1 = 1/3 un + 2/3 (u2 + dt L(u2)).                                                 */
+/* dt comes from the alpha of un.  On error the state and t are left unchanged.           */
+/* ------------------------------------------------------------------------------------ */
+int npo_step(const npo_problem* pb, double* u, double T, double* t, double* dt_out) {
+  int rc = validate(pb);
+  if (rc) return rc;
+  const long ny = pb->dim == 2 ? pb->ny : 1;
+  const size_t n = (size_t)pb->ncomp * (size_t)(pb->nx * ny);
+  double* L = (double*)malloc(sizeof(double) * n);
+  double* u1 = (double*)malloc(sizeof(double) * n);
+  double* u2 = (double*)malloc(sizeof(double) * n);
+  double alpha[2], dt;
+  rc = npo_rhs(pb, u, L, alpha);
+  if (rc) goto done;
+  dt = time_step(pb, alpha, T - *t);
+  for (size_t k = 0; k < n; ++k) u1[k] = u[k] + dt * L[k];
+  rc = npo_rhs(pb, u1, L, NULL);
+  if (rc) goto done;
+  for (size_t k = 0; k < n; ++k) u2[k] = 0.75 * u[k] + 0.25 * (u1[k] + dt * L[k]);
+  rc = npo_rhs(pb, u2, L, NULL);
+  if (rc) goto done;
+  for (size_t k = 0; k < n; ++k) u1[k] = 1.0 / 3.0 * u[k] + 2.0 / 3.0 * (u2[k] + dt * L[k]);
+  rc = finite_and_physical(pb, u1);
+  if (rc) goto done;
+  memcpy(u, u1, sizeof(double) * n);
+  *t = *t + dt;
+  if (dt_out) *dt_out = dt;
+done:
+  free(L);
+  free(u1);
+  free(u2);
+  return rc;
+}
+
+/* Run to T: steps until T - t <= 1e-12 max(1, |T|) or max_steps steps were taken. */
+int npo_solve(const npo_problem* pb, double* u, double T, long max_steps, double* t, long* nsteps) {
+  int rc = validate(pb);
+  if (rc) return rc;
+  double tol = 1e-12 * (fabs(T) > 1.0 ? fabs(T) : 1.0);
+  long k = 0;
+  while (T - *t > tol && (max_steps < 0 || k < max_steps)) {
+    rc = npo_step(pb, u, T, t, NULL);
+    if (rc) break;
+    ++k;
+  }
+  if (nsteps) *nsteps = k;
+  return rc;
+}

@@ -1,0 +1,282 @@
+"""Pins of the full oracle scheme (CPU only).
+
+* The paper's Table 5 (advection, k = 3) reproduced row by row, and design order 5.
+* Burgers before the shock against the exact solution by characteristics (Section 5.2,
+  Example 3) and, loosely, against Table 7.
+* 1D Euler: a smooth density wave (exact solution = translation) and Sod's problem against an
+  exact Riemann solver (Section 5.2, Example 4).
+* Invariants: conservation, constancy, mirror symmetry, the eps -> 0 reduction to WENO5-JS, and
+  the 2D dimension-by-dimension scheme's reduction to 1D and its x/y symmetry.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import exact_riemann as ER
+import oracle as O
+from conftest import load_golden
+from paper_1602_00182_amd import inputs as I
+
+
+# ---------------------------------------------------------------------------------------
+# Table 5 (Section 5.2, Example 1)
+# ---------------------------------------------------------------------------------------
+def _advection_errors(n, recon, dt_factor):
+    h = 2.0 / n
+    pb = O.Problem(nx=n, flux=O.ADVECTION, cfl=0.1, recon=recon, switch_mode=O.SWITCH_OFF,
+                   dt_fixed=dt_factor * h)
+    u, t, _ = O.solve(pb, I.sine_cell_averages(n), 0.5)
+    assert t == pytest.approx(0.5, abs=1e-12)
+    return O.errors(u, I.sine_cell_averages(n, phase=-0.5 * math.pi))
+
+
+_T5 = load_golden("table5_advection_k3.txt")
+
+
+@pytest.mark.parametrize("row", _T5, ids=[f"{r[0]}-{r[1]}" for r in _T5])
+def test_table5_reproduced(row):
+    method, n, l1, l2, linf = row
+    recon = O.WENO5_JS if method == "WENO-JS" else O.RBF_WENO5
+    dt_factor = 0.1 if method == "WENO-JS" else 0.01
+    g1, g2, ginf = _advection_errors(n, recon, dt_factor)
+    if n == 10:  # coarsest grid: only the L1 error is close
+        assert g1 == pytest.approx(l1, rel=0.10)
+        return
+    assert g1 == pytest.approx(l1, rel=0.03)
+    assert g2 == pytest.approx(l2, rel=0.05)
+    assert ginf == pytest.approx(linf, rel=0.25)
+
+
+def test_rbf_weno_design_order_five():
+    errs = [_advection_errors(n, O.RBF_WENO5, 0.01)[0] for n in (40, 80, 160)]
+    orders = [math.log2(errs[k] / errs[k + 1]) for k in range(2)]
+    assert min(orders) > 4.8, orders
+
+
+def test_rbf_weno_beats_weno_js():
+    """Section 5.2: the perturbed scheme is more accurate than WENO-JS at the same order."""
+    for n in (40, 80, 160):
+        assert _advection_errors(n, O.RBF_WENO5, 0.01)[0] < 0.5 * _advection_errors(n, O.WENO5_JS, 0.01)[0]
+
+
+# ---------------------------------------------------------------------------------------
+# Burgers (Section 5.2, Example 3)
+# ---------------------------------------------------------------------------------------
+def _burgers_exact_averages(n, t, q=10):
+    """Exact cell averages of the solution of u_t + (u^2/2)_x = 0, u0 = -sin(pi x), for
+    t < 1/pi: u(x, t) = u0(xi) with x = xi + u0(xi) t (Newton), Gauss-Legendre per cell."""
+    h = 2.0 / n
+    xg, wg = np.polynomial.legendre.leggauss(q)
+    out = np.zeros(n)
+    for i in range(n):
+        xs = -1 + i * h + (xg + 1) * h / 2
+        xi = xs.copy()
+        for _ in range(60):
+            F = xi - t * np.sin(math.pi * xi) - xs
+            dF = 1 - t * math.pi * np.cos(math.pi * xi)
+            xi -= F / dF
+        out[i] = np.dot(wg, -np.sin(math.pi * xi)) / 2
+    return out
+
+
+def _burgers_errors(n, recon, switch):
+    pb = O.Problem(nx=n, flux=O.BURGERS, cfl=0.1, recon=recon, switch_mode=switch)
+    u, _, _ = O.solve(pb, -I.sine_cell_averages(n), 0.2)
+    return O.errors(u, _burgers_exact_averages(n, 0.2))
+
+
+def test_burgers_converges_to_exact_solution():
+    errs = [_burgers_errors(n, O.RBF_WENO5, O.SWITCH_MONOTONE)[0] for n in (80, 160, 320)]
+    orders = [math.log2(errs[k] / errs[k + 1]) for k in range(2)]
+    assert errs[-1] < 5e-8
+    assert orders[-1] > 4.5, orders
+
+
+_T7 = load_golden("table7_burgers_k3.txt")
+
+
+@pytest.mark.parametrize("row", _T7, ids=[f"{r[0]}-{r[1]}" for r in _T7])
+def test_table7_soft(row):
+    method, n, l1, l2, linf = row
+    recon = O.WENO5_JS if method == "WENO-JS" else O.RBF_WENO5
+    g1, g2, ginf = _burgers_errors(n, recon, O.SWITCH_MONOTONE)
+    for got, ref in ((g1, l1), (g2, l2), (ginf, linf)):
+        assert ref / 3.5 < got < ref * 3.5
+
+
+def test_switch_keeps_eta_finite_at_burgers_critical_points():
+    """Without the monotone switch the shape parameter blows up where u_x -> 0 (the eta
+    denominator vanishes); Section 4's switch removes it there."""
+    on = _burgers_errors(320, O.RBF_WENO5, O.SWITCH_MONOTONE)[0]
+    assert on < 5e-8
+
+
+# ---------------------------------------------------------------------------------------
+# 1D Euler (Section 5.2, Example 4)
+# ---------------------------------------------------------------------------------------
+def _density_wave(n, t=0.0):
+    """rho = 1 + 0.2 sin(pi (x - t)), u = 1, p = 1: exact conservative cell averages."""
+    rho = 1.0 + 0.2 * I.sine_cell_averages(n, phase=-math.pi * t)
+    return np.concatenate([rho, rho * 1.0, 1.0 / 0.4 + 0.5 * rho * 1.0])
+
+
+def test_euler_density_wave_order():
+    errs = []
+    for n in (40, 80, 160):
+        h = 2.0 / n
+        pb = O.Problem(nx=n, flux=O.EULER, ncomp=3, dt_fixed=0.02 * h)
+        u, _, _ = O.solve(pb, _density_wave(n), 0.5)
+        errs.append(O.errors(u, _density_wave(n, 0.5))[0])
+    orders = [math.log2(errs[k] / errs[k + 1]) for k in range(2)]
+    assert min(orders) > 4.5, (errs, orders)
+
+
+@pytest.mark.parametrize("n,bound", [(200, 4e-3), (400, 2e-3)])
+def test_sod_against_exact_riemann_solution(n, bound):
+    w = I.sod(n)
+    pb = O.Problem(nx=n, flux=O.EULER, ncomp=3, bc=O.TRANSMISSIVE, cfl=0.5)
+    u, t, _ = O.solve(pb, w.u0, 0.2)
+    exact = ER.density_cell_averages(n, 0.2, (1.0, 0.0, 1.0), (0.125, 0.0, 0.1))
+    l1 = O.errors(u[:n], exact)[0]
+    assert l1 < bound
+    # non-oscillatory: the density stays within the initial bounds (small tolerance)
+    assert u[:n].min() > 0.125 - 5e-3 and u[:n].max() < 1.0 + 5e-3
+
+
+def test_euler_nonphysical_state_is_reported():
+    u0 = I.sod(50).u0.copy()
+    u0[2 * 50 + 10] = 0.0  # zero energy -> negative pressure
+    pb = O.Problem(nx=50, flux=O.EULER, ncomp=3, bc=O.TRANSMISSIVE)
+    with pytest.raises(O.OracleError) as e:
+        O.step(pb, u0, 0.1)
+    assert e.value.rc == O.ENONPHYSICAL
+
+
+def test_nonfinite_state_is_reported():
+    u0 = np.ones(32)
+    u0[3] = np.nan
+    with pytest.raises(O.OracleError) as e:
+        O.step(O.Problem(nx=32, flux=O.BURGERS), u0, 0.1)
+    assert e.value.rc == O.ENONFINITE
+
+
+# ---------------------------------------------------------------------------------------
+# Invariants
+# ---------------------------------------------------------------------------------------
+def test_periodic_conservation():
+    w = I.burgers_noisy(n=512, seed=7)
+    pb = O.Problem(nx=512, flux=O.BURGERS, cfl=0.5)
+    u, _, ns = O.solve(pb, w.u0, 0.3)
+    assert ns > 20
+    assert abs(u.sum() - w.u0.sum()) <= 1e-13 * np.abs(w.u0).sum()
+
+
+@pytest.mark.parametrize("flux,ncomp,state", [(O.BURGERS, 1, [0.7]), (O.ADVECTION, 1, [-1.3]),
+                                              (O.EULER, 3, [0.9, 0.3, 2.1])])
+def test_constant_state_has_zero_rhs(flux, ncomp, state):
+    n = 40
+    u = np.repeat(np.array(state), n)
+    for bc in (O.PERIODIC, O.TRANSMISSIVE):
+        L, _ = O.rhs(O.Problem(nx=n, flux=flux, ncomp=ncomp, bc=bc), u)
+        assert np.all(L == 0.0)
+
+
+def test_mirror_symmetry():
+    """x -> -x maps Burgers' u to -u(-x) and advection with speed a to speed -a: the result of
+    the mirrored problem is the mirror of the result (exercises the v^+ formulas)."""
+    w = I.burgers_noisy(n=256, seed=9)
+    pb = O.Problem(nx=256, flux=O.BURGERS, cfl=0.4)
+    u, _, _ = O.solve(pb, w.u0, 0.25)
+    um, _, _ = O.solve(pb, -w.u0[::-1], 0.25)
+    np.testing.assert_allclose(-um[::-1], u, rtol=0, atol=1e-13)
+    rng = np.random.default_rng(3)
+    u0 = np.cumsum(rng.normal(size=128)) * 0.05
+    pa = O.Problem(nx=128, flux=O.ADVECTION, speed_x=1.0, cfl=0.5)
+    pm = O.Problem(nx=128, flux=O.ADVECTION, speed_x=-1.0, cfl=0.5)
+    ua, _, _ = O.solve(pa, u0, 0.3)
+    ub, _, _ = O.solve(pm, u0[::-1], 0.3)
+    np.testing.assert_allclose(ub[::-1], ua, rtol=0, atol=1e-13)
+
+
+def test_vanishing_shape_parameter_recovers_weno_js():
+    """As eps -> 0 the perturbation vanishes (Section 3.5): with eps_M huge, eta ~ 1e-30 and the
+    RBF scheme equals WENO5-JS to 1e-14."""
+    w = I.burgers_noisy(n=256, seed=4)
+    a, _, _ = O.solve(O.Problem(nx=256, flux=O.BURGERS, eps_m=1e30, switch_mode=O.SWITCH_OFF), w.u0, 0.2)
+    b, _, _ = O.solve(O.Problem(nx=256, flux=O.BURGERS, recon=O.WENO5_JS), w.u0, 0.2)
+    assert np.max(np.abs(a - b)) <= 1e-14
+
+
+def test_switch_zeroes_eta_on_flagged_interfaces():
+    rng = np.random.default_rng(1)
+    line = rng.normal(size=64)
+    pb = O.Problem(nx=64, flux=O.BURGERS)
+    vm, vp, eta, flag = O.line_states(pb, line)
+    assert flag.sum() > 10
+    assert np.all(eta[flag == 1] == 0.0)
+    assert np.all(eta[flag == 0] != 0.0)
+
+
+# ---------------------------------------------------------------------------------------
+# 2D dimension-by-dimension scheme (Section 7, eq. 2DIntegral, one midpoint point per face)
+# ---------------------------------------------------------------------------------------
+def test_2d_euler_reduces_to_1d_for_y_independent_data():
+    n, ny = 64, 8
+    w = I.sod(n)
+    rho, m, E = w.u0.reshape(3, n)
+    U2 = np.stack([np.tile(rho, (ny, 1)), np.tile(m, (ny, 1)), np.zeros((ny, n)), np.tile(E, (ny, 1))])
+    dt = 0.2 * (2.0 / n)
+    p1 = O.Problem(nx=n, flux=O.EULER, ncomp=3, bc=O.TRANSMISSIVE, dt_fixed=dt)
+    p2 = O.Problem(nx=n, ny=ny, dim=2, flux=O.EULER, ncomp=4, bc=O.TRANSMISSIVE, x0=-1, x1=1, y0=0, y1=1,
+                   dt_fixed=dt)
+    u1, _, _ = O.solve(p1, w.u0, 0.05)
+    u2, _, _ = O.solve(p2, U2.reshape(-1), 0.05)
+    u2 = u2.reshape(4, ny, n)
+    for j in range(ny):
+        assert np.array_equal(u2[0, j], u1[:n])
+        assert np.array_equal(u2[1, j], u1[n:2 * n])
+        assert np.array_equal(u2[3, j], u1[2 * n:])
+    assert np.all(u2[2] == 0.0)
+
+
+def test_2d_euler_xy_symmetry():
+    n = 24
+    rng = np.random.default_rng(8)
+    xc = (np.arange(n) + 0.5) / n
+    X, Y = np.meshgrid(xc, xc)  # [j, i]
+    rho = 1 + 0.3 * np.sin(2 * np.pi * X + 0.4) * np.cos(2 * np.pi * Y) + 0.05 * rng.random((n, n))
+    u = 0.3 * np.cos(2 * np.pi * Y)
+    v = -0.2 * np.sin(2 * np.pi * X)
+    p = 1 + 0.2 * rng.random((n, n))
+    U = I.euler_prim_to_cons(rho, u, p, v=v)
+    UT = np.stack([U[0].T, U[2].T, U[1].T, U[3].T])  # swap x <-> y and u <-> v
+    pb = O.Problem(nx=n, ny=n, dim=2, flux=O.EULER, ncomp=4, bc=O.PERIODIC, x0=0, x1=1, y0=0, y1=1, cfl=0.4)
+    a, _, _ = O.solve(pb, U.reshape(-1), 0.05)
+    b, _, _ = O.solve(pb, UT.reshape(-1), 0.05)
+    a = a.reshape(4, n, n)
+    b = b.reshape(4, n, n)
+    bT = np.stack([b[0].T, b[2].T, b[1].T, b[3].T])
+    assert np.array_equal(a, bT)
+
+
+def test_2d_linear_advection_high_order():
+    """For a linear flux, 1D reconstruction of 2D cell averages gives face averages, so the
+    midpoint rule on faces is exact and the scheme keeps its 1D order (Section 7 example)."""
+    errs = []
+    for n in (16, 32, 64):
+        xc = (np.arange(n) + 0.5) / n
+        h = 1.0 / n
+        k = 2 * np.pi
+        fac = (math.sin(k * h / 2) / (k * h / 2)) ** 2
+
+        def avg(t):
+            X, Y = np.meshgrid(xc, xc)
+            return np.sin(k * (X + Y - 2 * t)) * fac
+
+        pb = O.Problem(nx=n, ny=n, dim=2, flux=O.ADVECTION, speed_x=1.0, speed_y=1.0, x0=0, x1=1, y0=0,
+                       y1=1, dt_fixed=0.02 * h)
+        u, _, _ = O.solve(pb, avg(0).reshape(-1), 0.25)
+        errs.append(O.errors(u, avg(0.25).reshape(-1))[0])
+    orders = [math.log2(errs[k] / errs[k + 1]) for k in range(2)]
+    assert min(orders) > 4.3, (errs, orders)
