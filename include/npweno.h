@@ -1,0 +1,138 @@
+/*
+ * npweno.h -- C ABI of the MI355X (gfx950) non-polynomial WENO5 finite-volume library.
+ *
+ * The library solves the hyperbolic conservation law u_t + div F(u) = 0 (Section 1 of Guo &
+ * Jung, "Non-polynomial ENO and WENO finite volume methods for hyperbolic conservation laws",
+ * arXiv:1602.00182) on a uniform grid of cell averages (Section 2) with:
+ *   - the k = 3 WENO reconstruction of eq. (weno_re) whose substencil coefficients are the
+ *     multiquadric-RBF perturbation of Table 3 (polynomial part + eta * perturbation part),
+ *   - the shape parameter eta = eps^2 dx^2 of the Table 3 caption, one per cell interface,
+ *     evaluated in double precision,
+ *   - the monotone-polynomial switch of Section 4 (eqs. root_value, adaptation) that sets
+ *     eta = 0 next to non-monotone 3-cell windows,
+ *   - Jiang-Shu nonlinear weights (eps_weno, Section 2), the global Lax-Friedrichs flux and
+ *     flux differencing of Section 5.1 (eq. PDE1), and the third-order TVD Runge-Kutta
+ *     method (Section 5.1),
+ *   - in 2D, the dimension-by-dimension finite-volume form of Section 7 (eq. 2DIntegral) with
+ *     one midpoint quadrature point per face.
+ * All compute runs in HIP kernels on the device; nothing falls back to the CPU.
+ *
+ * Conventions for every entry point:
+ *   - Return value: NPW_OK (0) or a negative NPW_E* code; nothing throws across the ABI.
+ *   - Device pointers are plain HIP device addresses (e.g. torch tensor data_ptr()); host
+ *     pointers are ordinary process memory.  The caller keeps ownership of every buffer it
+ *     passes; the library copies what it needs.
+ *   - hip_stream is a hipStream_t (NULL = the default stream).  All library work is ordered on
+ *     the solver's stream; calls that return host-visible results synchronize that stream.
+ *   - State layout (both directions): component-major structure of arrays.  1D:
+ *     u[c*nx + i]; 2D: u[(c*ny + j)*nx + i], c = 0..ncomp-1.  Element type is double for
+ *     NPW_FP64 and float for NPW_FP32.  Euler states are conservative: (rho, rho*u, E) in 1D
+ *     and (rho, rho*u, rho*v, E) in 2D.
+ *   - A solver is used by one host thread at a time.
+ */
+#ifndef NPWENO_H
+#define NPWENO_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define NPW_ABI_VERSION 1
+
+enum {
+  NPW_OK = 0,
+  NPW_EINVAL = -1,       /* bad argument; nothing was allocated or changed */
+  NPW_ENOMEM = -2,       /* device or host allocation failed */
+  NPW_EHIP = -3,         /* a HIP runtime call failed */
+  NPW_ENONFINITE = -4,   /* a cell average became NaN/Inf; state and t stay at the last good step */
+  NPW_ENONPHYSICAL = -5, /* Euler density or pressure <= 0; state and t stay at the last good step */
+  NPW_EBUSY = -6,        /* serving: request not finished yet */
+  NPW_ENOTFOUND = -7     /* serving: unknown request id */
+};
+
+enum { NPW_ADVECTION = 0, NPW_BURGERS = 1, NPW_EULER = 2 };  /* flux type */
+enum { NPW_PERIODIC = 0, NPW_TRANSMISSIVE = 1 };             /* boundary, all sides */
+enum { NPW_FP64 = 0, NPW_FP32 = 1 };  /* bulk precision; eta, the switch test, dt and t are always FP64 */
+enum { NPW_RBF_WENO5 = 0, NPW_WENO5_JS = 1 };                /* WENO5_JS: eta forced to zero */
+enum { NPW_SWITCH_MONOTONE = 0, NPW_SWITCH_OFF = 1 };        /* Section 4 switch on / off */
+
+typedef struct {
+  int32_t abi_version; /* must be NPW_ABI_VERSION */
+  int32_t dim;         /* 1 or 2 */
+  int32_t flux;        /* NPW_ADVECTION, NPW_BURGERS or NPW_EULER */
+  int32_t ncomp;       /* 1 for scalar fluxes, 3 for 1D Euler, 4 for 2D Euler */
+  int32_t bc;          /* NPW_PERIODIC or NPW_TRANSMISSIVE (copy of the edge cell) */
+  int32_t precision;   /* NPW_FP64 or NPW_FP32 */
+  int32_t recon;       /* NPW_RBF_WENO5 or NPW_WENO5_JS */
+  int32_t switch_mode; /* NPW_SWITCH_MONOTONE or NPW_SWITCH_OFF */
+  int64_t nx, ny;      /* cells per direction; ny is ignored (treated as 1) in 1D */
+  double x0, x1, y0, y1;   /* domain; y0, y1 ignored in 1D */
+  double speed_x, speed_y; /* advection velocity (NPW_ADVECTION) */
+  double gamma;            /* ratio of specific heats (NPW_EULER), > 1 */
+  double cfl;              /* dt = cfl*dx/alpha (1D), cfl/(alpha_x/dx + alpha_y/dy) (2D) */
+  double eps_weno;         /* epsilon of the nonlinear weights, Section 2 (1e-6) */
+  double eps_m;            /* eps_M of the eta denominator (> 0), added with its sign (1e-12) */
+  double dt_fixed;         /* > 0: use this dt instead of the CFL rule (accuracy studies) */
+} npw_params;
+
+typedef struct {
+  double t;          /* current time */
+  int64_t nsteps;    /* RK3 steps taken since create / write */
+  double alpha[2];   /* Lax-Friedrichs alpha of the current state (x, y) */
+  double mass[4];    /* sum over cells of u_c * cell area, per component (FP64 on device) */
+  int32_t err;       /* sticky error code of the last failing step (0 if none) */
+  int32_t err_stage; /* RK stage (1..3) where it was detected, 0 at the initial state */
+} npw_stats;
+
+typedef struct npw_solver npw_solver;  /* opaque; owns all device state */
+typedef struct npw_server npw_server;  /* opaque; serving loop */
+
+int npweno_abi_version(void);
+const char* npweno_strerror(int code);
+
+/* Fill *p with the defaults: abi_version, dim 1, advection with speed 1 on [-1,1], periodic,
+ * FP64, RBF-WENO5 with the monotone switch, cfl 0.5, eps_weno 1e-6, eps_m 1e-12, gamma 1.4. */
+void npweno_default_params(npw_params* p);
+
+/* Create a solver for one grid and copy the initial cell averages u0 (layout above, element
+ * type from p->precision; device memory if u0_on_device, else host memory).  t starts at 0.
+ * Validates every parameter before allocating: NPW_EINVAL on a bad value, dimension/ncomp/flux
+ * mismatch or NULL pointer.  Returns NPW_ENONFINITE / NPW_ENONPHYSICAL (and no solver) if u0
+ * already violates those conditions. */
+int npweno_create(const npw_params* p, const void* u0, int u0_on_device, void* hip_stream,
+                  npw_solver** out);
+
+/* One SSP-RK3 step (Section 5.1) with dt = min(CFL rule, t_final - t); does nothing when
+ * t_final - t <= 1e-12 max(1, |t_final|).  *dt_taken (may be NULL) receives the step taken
+ * (0 if none).  Synchronizes the stream. */
+int npweno_step(npw_solver* s, double t_final, double* dt_taken);
+
+/* Advance to t_final (same clipping and stopping rule) or until max_steps more steps were taken
+ * (max_steps < 0: no limit).  Steps run as captured HIP graphs of several steps each; the
+ * host only polls completion between graph replays.  stats may be NULL. */
+int npweno_solve(npw_solver* s, double t_final, int64_t max_steps, npw_stats* stats);
+
+/* Semi-discrete right-hand side L(u) = -(F_{i+1/2} - F_{i-1/2})/dx [- (G_{j+1/2}-G_{j-1/2})/dy]
+ * of eq. (PDE1) for the current state, with alpha of the current state; written to L_out in
+ * the state layout (device pointer if out_on_device).  Synchronizes the stream. */
+int npweno_rhs(npw_solver* s, void* L_out, int out_on_device);
+
+/* Copy the current state out (device pointer if out_on_device).  Synchronizes the stream. */
+int npweno_read(const npw_solver* s, void* u_out, int out_on_device);
+
+/* Replace the state (same layout/type as create) and set the time to t; resets the step count
+ * and any sticky error.  Used to restart from a checkpoint. */
+int npweno_write(npw_solver* s, const void* u, int on_device, double t);
+
+/* Time, step count, alpha and per-component sums of the current state. */
+int npweno_get_stats(const npw_solver* s, npw_stats* stats);
+
+void npweno_destroy(npw_solver* s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,256 @@
+// npw_device.h -- per-cell / per-interface arithmetic of the scheme, as device functions.
+//
+// Two flavours share this header:
+//   * double bulk (EXACT = true): every operation in the order the scheme states it, built
+//     without FP contraction, so results are reproducible bit for bit.
+//   * float bulk (EXACT = false): the same quantities with shared reciprocals and FMA; the
+//     shape parameter and the switch decision stay in double precision.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "npw_internal.h"
+
+namespace npw {
+
+// Ghost-cell index (Section 1 leaves the boundary treatment open): periodic wrap, or a copy of
+// the edge cell (transmissive).
+__device__ __forceinline__ long long ghost_index(long long k, long long n, int bc) {
+  if (k >= 0 && k < n) return k;
+  if (bc == 0) {
+    long long m = k % n;
+    return m < 0 ? m + n : m;
+  }
+  return k < 0 ? 0 : n - 1;
+}
+
+// Monotone-polynomial test of Section 4 (eqs. root_value and adaptation) on the window
+// (u_{j-1}, u_j, u_{j+1}): the quadratic reconstruction has its extremum at
+// x_p/dx = (-2u_{j-1} + 3u_j - u_{j+1}) / (-u_{j-1} + 2u_j - u_{j+1}) from x_{j-3/2}; the window is
+// not monotone when 0 < x_p/dx < 3.  Division by zero (linear data) gives inf/NaN, which fails
+// the strict test.  Double precision, uncontracted: the decision is the one the quotient makes.
+__device__ __forceinline__ int monotone_flag(double um1, double u0, double up1) {
+#pragma clang fp contract(off)
+  double num = -2.0 * um1 + 3.0 * u0 - up1;
+  double den = -um1 + 2.0 * u0 - up1;
+  double xp = num / den;
+  return (xp > 0.0 && xp < 3.0) ? 1 : 0;
+}
+
+// Shape parameter eta = eps^2 dx^2 at x_{i+1/2} (Table 3 caption) from u_{i-1}..u_{i+2}:
+// third over (weighted) first undivided difference; eps_M is added with the sign of the
+// denominator so that it never crosses zero.  Double precision, uncontracted.
+__device__ __forceinline__ double eta_ratio(double um1, double u0, double up1, double up2, double eps_m) {
+#pragma clang fp contract(off)
+  double num = um1 - 3.0 * u0 + 3.0 * up1 - up2;
+  double den = um1 - 15.0 * u0 + 15.0 * up1 - up2;
+  if (den >= 0.0)
+    den = den + eps_m;
+  else
+    den = den - eps_m;
+  return num / den;
+}
+
+// Jiang-Shu smoothness indicators of cell i from (a..e) = u_{i-2}..u_{i+2}; b0 for the stencil
+// {i..i+2}, b1 for {i-1..i+1}, b2 for {i-2..i}.
+template <typename R>
+__device__ __forceinline__ void smoothness(R a, R b, R c, R d, R e, R& b0, R& b1, R& b2) {
+  R t;
+  t = c - R(2.0) * d + e;
+  b0 = R(13.0 / 12.0) * t * t;
+  t = R(3.0) * c - R(4.0) * d + e;
+  b0 = b0 + R(0.25) * t * t;
+  t = b - R(2.0) * c + d;
+  b1 = R(13.0 / 12.0) * t * t;
+  t = b - d;
+  b1 = b1 + R(0.25) * t * t;
+  t = a - R(2.0) * b + c;
+  b2 = R(13.0 / 12.0) * t * t;
+  t = a - R(4.0) * b + R(3.0) * c;
+  b2 = b2 + R(0.25) * t * t;
+}
+
+// Table 3 row r at x_{i+1/2} applied to (w0, w1, w2) = (u_{i-r}, u_{i-r+1}, u_{i-r+2}):
+// sum_j (c_rj + eta p_rj) w_j, with the polynomial part c_rj (left table; the r = -1, j = 0 entry
+// is 11/6) and the multiquadric perturbation p_rj (right table).
+template <typename R, int ROW>
+__device__ __forceinline__ R table3_row(R w0, R w1, R w2, R eta) {
+  if constexpr (ROW == -1)
+    return (R(11.0 / 6.0) + eta * R(-9.0 / 2.0)) * w0 + (R(-7.0 / 6.0) + eta * R(6.0)) * w1 +
+           (R(1.0 / 3.0) + eta * R(-3.0 / 2.0)) * w2;
+  else if constexpr (ROW == 0)
+    return (R(1.0 / 3.0) + eta * R(5.0 / 6.0)) * w0 + (R(5.0 / 6.0) + eta * R(-2.0 / 3.0)) * w1 +
+           (R(-1.0 / 6.0) + eta * R(-1.0 / 6.0)) * w2;
+  else if constexpr (ROW == 1)
+    return (R(-1.0 / 6.0) + eta * R(-1.0 / 6.0)) * w0 + (R(5.0 / 6.0) + eta * R(-2.0 / 3.0)) * w1 +
+           (R(1.0 / 3.0) + eta * R(5.0 / 6.0)) * w2;
+  else
+    return (R(1.0 / 3.0) + eta * R(-3.0 / 2.0)) * w0 + (R(-7.0 / 6.0) + eta * R(6.0)) * w1 +
+           (R(11.0 / 6.0) + eta * R(-9.0 / 2.0)) * w2;
+}
+
+// Both reconstructed values of cell i from its five-cell window (a..e) = u_{i-2}..u_{i+2}:
+//   vm = v^-_{i+1/2} (rows 0, 1, 2 with eta_{i+1/2}, linear weights 3/10, 3/5, 1/10),
+//   vp = v^+_{i-1/2} (rows -1, 0, 1 with eta_{i-1/2}, linear weights 1/10, 3/5, 3/10),
+// combined with the nonlinear weights of eq. (weno_re), alpha_r = d_r / (eps + beta_r)^2.
+// Exact flavour: the operation order of the definition (alpha_r, then w_r = alpha_r / sum,
+// then sum w_r q_r).
+__device__ __forceinline__ void weno_pair_exact(double a, double b, double c, double d, double e,
+                                                double eta_r, double eta_l, double eps, bool want_m,
+                                                bool want_p, double& vm, double& vp) {
+#pragma clang fp contract(off)
+  double b0, b1, b2;
+  smoothness<double>(a, b, c, d, e, b0, b1, b2);
+  const double s0 = (eps + b0) * (eps + b0), s1 = (eps + b1) * (eps + b1), s2 = (eps + b2) * (eps + b2);
+  if (want_m) {
+    double q0 = table3_row<double, 0>(c, d, e, eta_r);
+    double q1 = table3_row<double, 1>(b, c, d, eta_r);
+    double q2 = table3_row<double, 2>(a, b, c, eta_r);
+    double a0 = (3.0 / 10.0) / s0, a1 = (3.0 / 5.0) / s1, a2 = (1.0 / 10.0) / s2;
+    double s = a0 + a1 + a2;
+    double w0 = a0 / s, w1 = a1 / s, w2 = a2 / s;
+    vm = w0 * q0 + w1 * q1 + w2 * q2;
+  }
+  if (want_p) {
+    double q0 = table3_row<double, -1>(c, d, e, eta_l);
+    double q1 = table3_row<double, 0>(b, c, d, eta_l);
+    double q2 = table3_row<double, 1>(a, b, c, eta_l);
+    double a0 = (1.0 / 10.0) / s0, a1 = (3.0 / 5.0) / s1, a2 = (3.0 / 10.0) / s2;
+    double s = a0 + a1 + a2;
+    double w0 = a0 / s, w1 = a1 / s, w2 = a2 / s;
+    vp = w0 * q0 + w1 * q1 + w2 * q2;
+  }
+}
+
+// Fast float flavour: one reciprocal per (eps + beta_r)^2 shared by both sides, normalisation
+// by one reciprocal per side, and the perturbation split off as eta * (sum_j p_rj w_j).
+__device__ __forceinline__ void weno_pair_fast(float a, float b, float c, float d, float e, float eta_r,
+                                               float eta_l, float eps, bool want_m, bool want_p, float& vm,
+                                               float& vp) {
+  float b0, b1, b2;
+  smoothness<float>(a, b, c, d, e, b0, b1, b2);
+  const float g0 = eps + b0, g1 = eps + b1, g2 = eps + b2;
+  const float i0 = __builtin_amdgcn_rcpf(g0 * g0);
+  const float i1 = __builtin_amdgcn_rcpf(g1 * g1);
+  const float i2 = __builtin_amdgcn_rcpf(g2 * g2);
+  if (want_m) {
+    float q0 = table3_row<float, 0>(c, d, e, eta_r);
+    float q1 = table3_row<float, 1>(b, c, d, eta_r);
+    float q2 = table3_row<float, 2>(a, b, c, eta_r);
+    float a0 = 0.3f * i0, a1 = 0.6f * i1, a2 = 0.1f * i2;
+    vm = (a0 * q0 + a1 * q1 + a2 * q2) * __builtin_amdgcn_rcpf(a0 + a1 + a2);
+  }
+  if (want_p) {
+    float q0 = table3_row<float, -1>(c, d, e, eta_l);
+    float q1 = table3_row<float, 0>(b, c, d, eta_l);
+    float q2 = table3_row<float, 1>(a, b, c, eta_l);
+    float a0 = 0.1f * i0, a1 = 0.6f * i1, a2 = 0.3f * i2;
+    vp = (a0 * q0 + a1 * q1 + a2 * q2) * __builtin_amdgcn_rcpf(a0 + a1 + a2);
+  }
+}
+
+// Physical flux along direction DIR (0: x, 1: y) of the state U[0..M-1] (Section 5.1; Euler as in
+// Example 4, conservative variables).
+template <typename R, int FLUX, int M, int DIR>
+__device__ __forceinline__ void phys_flux(const R* U, R speed, R gamma, R* F) {
+  if constexpr (FLUX == kAdvection) {
+    F[0] = speed * U[0];
+  } else if constexpr (FLUX == kBurgers) {
+    F[0] = R(0.5) * U[0] * U[0];
+  } else if constexpr (M == 3) {
+    R rho = U[0], m = U[1], E = U[2];
+    R u = m / rho;
+    R p = (gamma - R(1.0)) * (E - R(0.5) * rho * u * u);
+    F[0] = m;
+    F[1] = m * u + p;
+    F[2] = (E + p) * u;
+  } else {
+    R rho = U[0], mx = U[1], my = U[2], E = U[3];
+    R u = mx / rho, v = my / rho;
+    R p = (gamma - R(1.0)) * (E - R(0.5) * rho * (u * u + v * v));
+    if constexpr (DIR == 0) {
+      F[0] = mx;
+      F[1] = mx * u + p;
+      F[2] = my * u;
+      F[3] = (E + p) * u;
+    } else {
+      F[0] = my;
+      F[1] = mx * v;
+      F[2] = my * v + p;
+      F[3] = (E + p) * v;
+    }
+  }
+}
+
+// Global Lax-Friedrichs flux h(a, b) = 1/2 [f(a) + f(b) - alpha (b - a)] (Section 5.1).
+template <typename R, int FLUX, int M, int DIR>
+__device__ __forceinline__ void lf_flux(const R* A, const R* B, R alpha, R speed, R gamma, R* H) {
+  R fa[M], fb[M];
+  phys_flux<R, FLUX, M, DIR>(A, speed, gamma, fa);
+  phys_flux<R, FLUX, M, DIR>(B, speed, gamma, fb);
+#pragma unroll
+  for (int c = 0; c < M; ++c) H[c] = R(0.5) * (fa[c] + fb[c] - alpha * (B[c] - A[c]));
+}
+
+// Spectral radius of dF/dU along DIR at a cell-average state, plus validity: returns false for
+// a non-finite state (code 1) or a non-physical Euler state (code 2).
+template <typename R, int FLUX, int M, int DIR>
+__device__ __forceinline__ R spectral_radius(const R* U, R speed, R gamma, int& bad) {
+  bad = 0;
+#pragma unroll
+  for (int c = 0; c < M; ++c)
+    if (!isfinite(U[c])) bad = 1;
+  if (bad) return R(0);
+  if constexpr (FLUX == kAdvection) {
+    return fabs(speed);
+  } else if constexpr (FLUX == kBurgers) {
+    return fabs(U[0]);
+  } else if constexpr (M == 3) {
+    R rho = U[0], u = U[1] / rho;
+    R p = (gamma - R(1.0)) * (U[2] - R(0.5) * rho * u * u);
+    if (!(rho > R(0)) || !(p > R(0))) {
+      bad = 2;
+      return R(0);
+    }
+    return fabs(u) + sqrt(gamma * p / rho);
+  } else {
+    R rho = U[0], u = U[1] / rho, v = U[2] / rho;
+    R p = (gamma - R(1.0)) * (U[3] - R(0.5) * rho * (u * u + v * v));
+    if (!(rho > R(0)) || !(p > R(0))) {
+      bad = 2;
+      return R(0);
+    }
+    return fabs(DIR == 0 ? u : v) + sqrt(gamma * p / rho);
+  }
+}
+
+// Time step of the step starting at t (Section 5.1's CFL rule, clipped to the remaining time).
+__device__ __forceinline__ double step_dt(const InstDev* I, double t, double ax, double ay) {
+#pragma clang fp contract(off)
+  double dt;
+  if (I->dt_fixed > 0.0)
+    dt = I->dt_fixed;
+  else if (I->dim == 1)
+    dt = I->cfl * I->dx / ax;
+  else
+    dt = I->cfl / (ax / I->dx + ay / I->dy);
+  double rem = I->T - t;
+  if (dt > rem) dt = rem;
+  return dt;
+}
+
+__device__ __forceinline__ double bits_to_double(unsigned long long b) { return __longlong_as_double((long long)b); }
+__device__ __forceinline__ unsigned long long double_to_bits(double d) {
+  return (unsigned long long)__double_as_longlong(d);
+}
+
+// Max of a non-negative value over the wavefront (64 lanes), on the bit pattern.
+__device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    unsigned long long o = __shfl_xor(v, off, 64);
+    v = o > v ? o : v;
+  }
+  return v;
+}
+
+}  // namespace npw

@@ -1,0 +1,46 @@
+// Kernel instantiations for the double bulk precision.
+#include "npw_kernels.h"
+
+namespace npw {
+
+template <int BS>
+static hipError_t launch_stage_bs(int flux, int ncomp, const StageArgs& a, hipStream_t s) {
+  if (a.ntiles <= 0) return hipSuccess;
+  const dim3 grid(a.ntiles), block(BS);
+  if (flux == kAdvection && ncomp == 1)
+    stage1d_kernel<double, kAdvection, 1, BS><<<grid, block, 0, s>>>(a);
+  else if (flux == kBurgers && ncomp == 1)
+    stage1d_kernel<double, kBurgers, 1, BS><<<grid, block, 0, s>>>(a);
+  else if (flux == kEuler && ncomp == 3)
+    stage1d_kernel<double, kEuler, 3, BS><<<grid, block, 0, s>>>(a);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t launch_stage_f64(int flux, int ncomp, int block, const StageArgs& a, hipStream_t s) {
+  switch (block) {
+    case 128: return launch_stage_bs<128>(flux, ncomp, a, s);
+    case 256: return launch_stage_bs<256>(flux, ncomp, a, s);
+    case 512: return launch_stage_bs<512>(flux, ncomp, a, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_init_f64(int flux, int ncomp, InstDev* inst, int ninst, void* P0, void* P1, hipStream_t s) {
+  if (ninst <= 0) return hipSuccess;
+  const dim3 grid(ninst), block(256);
+  if (flux == kAdvection && ncomp == 1)
+    init_kernel<double, kAdvection, 1><<<grid, block, 0, s>>>(inst, P0, P1);
+  else if (flux == kBurgers && ncomp == 1)
+    init_kernel<double, kBurgers, 1><<<grid, block, 0, s>>>(inst, P0, P1);
+  else if (flux == kEuler && ncomp == 3)
+    init_kernel<double, kEuler, 3><<<grid, block, 0, s>>>(inst, P0, P1);
+  else if (flux == kEuler && ncomp == 4)
+    init_kernel<double, kEuler, 4><<<grid, block, 0, s>>>(inst, P0, P1);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+}  // namespace npw

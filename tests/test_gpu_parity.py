@@ -1,0 +1,323 @@
+"""GPU parity of the HIP path (through the C ABI) against the FP64 CPU oracle.
+
+Bars: the double-precision path evaluates every operation in the scheme's order without FP
+contraction, so it is compared at 1e-12 (and is expected to agree bit for bit); the float
+bulk path is compared at 1e-5 on smooth data.  Grids span several workgroup tiles with a ragged
+tail, both boundary kinds, every flux, both reconstructions and the switch on and off.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1602_00182_amd import binding as B
+from paper_1602_00182_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-12
+TOL32 = 1e-5
+
+
+def _say(msg):
+    print(f"[case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+def _oracle_problem(w, **over):
+    kw = dict(nx=w.nx, flux=w.flux, dim=w.dim, ny=w.ny, ncomp=w.ncomp, bc=w.bc, x0=w.x0, x1=w.x1, y0=w.y0,
+              y1=w.y1, speed_x=w.speed_x, speed_y=w.speed_y, gamma=w.gamma, cfl=w.cfl, eps_weno=w.eps_weno,
+              eps_m=w.eps_m, recon=w.recon, switch_mode=w.switch_mode, dt_fixed=w.dt_fixed)
+    kw.update(over)
+    return O.Problem(**kw)
+
+
+def _solver(w, precision=B.FP64, u0=None):
+    u = w.u0 if u0 is None else u0
+    if precision == B.FP32:
+        u = np.asarray(u, dtype=np.float32)
+    return B.Solver(u, **B.workload_params(w, precision))
+
+
+def _random_burgers(n, seed):
+    rng = np.random.default_rng(seed)
+    return 0.5 + I.sine_cell_averages(n) + 0.3 * rng.uniform(-1, 1, n) * (rng.random(n) < 0.1)
+
+
+# ---------------------------------------------------------------------------------------
+# one evaluation of L(u): every interface of every tile, bit for bit in double
+# ---------------------------------------------------------------------------------------
+@pytest.mark.parametrize("n", [1, 5, 80, 253, 254, 255, 1000, 4099])
+@pytest.mark.parametrize("bc", [I.PERIODIC, I.TRANSMISSIVE])
+def test_rhs_burgers_fp64(n, bc):
+    _say(f"rhs burgers fp64 n={n} bc={bc}")
+    u0 = _random_burgers(n, n)
+    w = I.Workload(name="r", nx=n, flux=I.BURGERS, u0=u0, T=1.0, bc=bc)
+    with _solver(w) as s:
+        L = s.rhs()
+    Lo, _ = O.rhs(_oracle_problem(w), u0)
+    assert np.max(np.abs(L - Lo)) <= TOL64 * max(1.0, np.abs(Lo).max())
+    assert np.array_equal(L, Lo)
+
+
+@pytest.mark.parametrize("recon,sw", [(I.RBF_WENO5, I.SWITCH_MONOTONE), (I.RBF_WENO5, I.SWITCH_OFF),
+                                      (I.WENO5_JS, I.SWITCH_MONOTONE)])
+def test_rhs_modes_fp64(recon, sw):
+    _say(f"rhs modes recon={recon} sw={sw}")
+    n = 777
+    u0 = _random_burgers(n, 3)
+    w = I.Workload(name="r", nx=n, flux=I.BURGERS, u0=u0, T=1.0, recon=recon, switch_mode=sw)
+    with _solver(w) as s:
+        L = s.rhs()
+    Lo, _ = O.rhs(_oracle_problem(w), u0)
+    assert np.array_equal(L, Lo)
+
+
+def test_rhs_euler_fp64():
+    _say("rhs euler fp64")
+    w = I.euler_riemann_batch(count=1, seed=11, nmin=700, nmax=700)[0]
+    with _solver(w) as s:
+        L = s.rhs()
+    Lo, _ = O.rhs(_oracle_problem(w), w.u0)
+    assert np.max(np.abs(L - Lo)) <= TOL64 * max(1.0, np.abs(Lo).max())
+
+
+# ---------------------------------------------------------------------------------------
+# whole solves
+# ---------------------------------------------------------------------------------------
+@pytest.mark.parametrize("sw", [I.SWITCH_OFF, I.SWITCH_MONOTONE])
+def test_advection_n80_to_T2_fp64(sw):
+    """Smallest workload: N = 80, sin(pi x), CFL 0.5, T = 2 (160 steps)."""
+    _say(f"advection N80 T2 fp64 sw={sw}")
+    w = I.advection_sine(80, T=2.0, cfl=0.5, switch_mode=sw)
+    with _solver(w) as s:
+        st = s.solve(w.T)
+        u = s.read()
+    uo, to, no = O.solve(_oracle_problem(w), w.u0, w.T)
+    assert st["nsteps"] == no and st["t"] == to
+    assert np.max(np.abs(u - uo)) <= TOL64
+    assert np.array_equal(u, uo)
+
+
+def test_burgers_noisy_steps_fp64():
+    _say("burgers noisy 2000 cells 60 steps fp64")
+    w = I.burgers_noisy(n=2000, seed=2)
+    with _solver(w) as s:
+        st = s.solve(w.T, max_steps=60)
+        u = s.read()
+    uo, to, no = O.solve(_oracle_problem(w), w.u0, w.T, max_steps=60)
+    assert st["nsteps"] == no == 60
+    assert np.max(np.abs(u - uo)) <= TOL64
+    assert np.array_equal(u, uo)
+
+
+def test_sod_fp64():
+    _say("sod N600 fp64")
+    w = I.sod(600, T=0.2, cfl=0.5)
+    with _solver(w) as s:
+        st = s.solve(w.T)
+        u = s.read()
+    uo, to, no = O.solve(_oracle_problem(w), w.u0, w.T)
+    assert st["nsteps"] == no
+    assert np.max(np.abs(u - uo)) <= TOL64
+
+
+def test_euler_riemann_instance_fp64():
+    _say("euler riemann instance fp64")
+    w = I.euler_riemann_batch(count=2, seed=3)[1]
+    with _solver(w) as s:
+        s.solve(w.T, max_steps=100)
+        u = s.read()
+    uo, _, _ = O.solve(_oracle_problem(w), w.u0, w.T, max_steps=100)
+    assert np.max(np.abs(u - uo)) <= TOL64
+
+
+def test_step_api_and_clipping():
+    _say("step api")
+    w = I.advection_sine(80, T=2.0)
+    with _solver(w) as s:
+        dt = s.step(2.0)
+        assert dt == pytest.approx(0.5 * (2.0 / 80) / 1.0)
+        dt2 = s.step(dt + 1e-3)  # clipped to the remaining 1e-3
+        assert dt2 == pytest.approx(1e-3, rel=1e-9)
+        assert s.step(dt + 1e-3) == 0.0  # already there
+        u = s.read()
+    uo, _, _ = O.step(_oracle_problem(w), w.u0, 2.0)
+    uo, _, _ = O.step(_oracle_problem(w), uo, dt + 1e-3, t=dt)
+    assert np.array_equal(u, uo)
+
+
+# ---------------------------------------------------------------------------------------
+# float bulk with double shape parameter
+# ---------------------------------------------------------------------------------------
+def test_advection_n80_fp32():
+    _say("advection N80 fp32")
+    w = I.advection_sine(80, T=2.0, switch_mode=I.SWITCH_OFF)
+    with _solver(w, B.FP32) as s:
+        s.solve(w.T)
+        u = s.read().astype(np.float64)
+    uo, _, _ = O.solve(_oracle_problem(w), np.asarray(w.u0, np.float32).astype(np.float64), w.T)
+    assert np.max(np.abs(u - uo)) <= TOL32
+
+
+def test_burgers_smooth_fp32():
+    _say("burgers smooth fp32")
+    w = I.burgers_sine(1024, T=0.2, cfl=0.5)
+    with _solver(w, B.FP32) as s:
+        s.solve(w.T)
+        u = s.read().astype(np.float64)
+    uo, _, _ = O.solve(_oracle_problem(w), np.asarray(w.u0, np.float32).astype(np.float64), w.T)
+    assert np.max(np.abs(u - uo)) <= TOL32
+
+
+def test_rhs_fp32_one_stage():
+    _say("rhs fp32")
+    n = 1000
+    u0 = I.sine_cell_averages(n) * 0.8 + 0.1
+    w = I.Workload(name="r", nx=n, flux=I.BURGERS, u0=u0, T=1.0)
+    u32 = np.asarray(u0, np.float32)
+    with _solver(w, B.FP32, u0=u32) as s:
+        L = s.rhs().astype(np.float64)
+    Lo, _ = O.rhs(_oracle_problem(w), u32.astype(np.float64))
+    assert np.max(np.abs(L - Lo)) <= 1e-4 * np.abs(Lo).max()
+
+
+def test_sod_fp32():
+    _say("sod fp32")
+    w = I.sod(600, T=0.2)
+    with _solver(w, B.FP32) as s:
+        s.solve(w.T)
+        u = s.read().astype(np.float64)
+    uo, _, _ = O.solve(_oracle_problem(w), np.asarray(w.u0, np.float32).astype(np.float64), w.T)
+    assert np.mean(np.abs(u - uo)) <= 1e-5
+
+
+# ---------------------------------------------------------------------------------------
+# invariants, errors, checkpoint
+# ---------------------------------------------------------------------------------------
+def test_conservation_fp64():
+    _say("conservation fp64")
+    w = I.burgers_noisy(n=4096, seed=5)
+    with _solver(w) as s:
+        m0 = s.stats()["mass"][0]
+        st = s.solve(0.3)
+        m1 = st["mass"][0]
+    assert abs(m1 - m0) <= 1e-13 * np.abs(w.u0).sum() * w.dx
+
+
+def test_constant_state_rhs_is_zero():
+    _say("constant state")
+    for flux, m, st in [(I.BURGERS, 1, [0.7]), (I.EULER, 3, [0.9, 0.3, 2.1])]:
+        n = 600
+        u0 = np.repeat(np.array(st), n)
+        w = I.Workload(name="c", nx=n, flux=flux, ncomp=m, u0=u0, T=1.0, bc=I.TRANSMISSIVE)
+        with _solver(w) as s:
+            assert np.all(s.rhs() == 0.0)
+
+
+def test_nonfinite_initial_state_rejected():
+    _say("nonfinite initial")
+    u0 = I.sine_cell_averages(300)
+    u0[17] = np.nan
+    with pytest.raises(B.NpwError) as e:
+        B.Solver(u0, nx=300, flux=B.BURGERS)
+    assert e.value.code == B.ENONFINITE
+
+
+def test_blowup_reports_error_and_keeps_last_good_step():
+    _say("blowup cfl 40")
+    w = I.burgers_noisy(n=512, seed=1, cfl=40.0, T=1000.0)
+    with _solver(w) as s:
+        with pytest.raises(B.NpwError) as e:
+            s.solve(w.T)
+        assert e.value.code == B.ENONFINITE
+        st = s.stats()
+        u = s.read()
+    n_good = st["nsteps"]
+    uo, to, _ = O.solve(_oracle_problem(w), w.u0, w.T, max_steps=n_good)
+    assert np.all(np.isfinite(u))
+    assert np.array_equal(u, uo) and st["t"] == to
+    with pytest.raises(O.OracleError):
+        O.step(_oracle_problem(w), uo, w.T, t=to)
+
+
+def test_nonphysical_euler_reported():
+    _say("euler nonphysical")
+    u0 = I.sod(200).u0.copy()
+    u0[200 + 50] = 1.0  # momentum 1 with energy 0.1: pressure 0.4 (0.1 - 0.5) < 0
+    u0[2 * 200 + 50] = 0.1
+    with pytest.raises(B.NpwError) as e:
+        B.Solver(u0, **B.workload_params(I.sod(200)))
+    assert e.value.code == B.ENONPHYSICAL
+
+
+def test_checkpoint_resume_is_bitwise():
+    _say("checkpoint")
+    w = I.burgers_noisy(n=3000, seed=6)
+    with _solver(w) as s:
+        s.solve(0.2)
+        ref = s.read()
+    with _solver(w) as s:
+        s.solve(0.2, max_steps=37)
+        mid = s.read()
+        t_mid = s.stats()["t"]
+    with _solver(w, u0=mid) as s:
+        s.write(mid, t_mid)
+        s.solve(0.2)
+        got = s.read()
+    assert np.array_equal(got, ref)
+
+
+def test_device_tensors_and_torch_stream():
+    _say("torch device tensors")
+    import torch
+    w = I.burgers_noisy(n=5000, seed=8)
+    u0 = torch.tensor(w.u0, dtype=torch.float64, device="cuda")
+    s = B.Solver(u0, **B.workload_params(w))
+    s.solve(0.1, max_steps=20)
+    out = torch.empty_like(u0)
+    s.read(out)
+    torch.cuda.synchronize()
+    uo, _, _ = O.solve(_oracle_problem(w), w.u0, 0.1, max_steps=20)
+    assert np.array_equal(out.cpu().numpy(), uo)
+    s.close()
+
+
+# ---------------------------------------------------------------------------------------
+# the headline workload at full size: N = 65536 Burgers, in the benchmark's launch configuration
+# ---------------------------------------------------------------------------------------
+def test_full_size_burgers_rhs_and_steps_fp64():
+    _say("full size burgers 65536 fp64")
+    w = I.burgers_noisy()
+    with _solver(w) as s:
+        L = s.rhs()
+        Lo, _ = O.rhs(_oracle_problem(w), w.u0)
+        assert np.array_equal(L, Lo)
+        s.solve(w.T, max_steps=30)
+        u = s.read()
+    uo, _, _ = O.solve(_oracle_problem(w), w.u0, w.T, max_steps=30)
+    assert np.array_equal(u, uo)
+
+
+def test_full_size_burgers_fp32_steps():
+    _say("full size burgers 65536 fp32")
+    w = I.burgers_noisy()
+    u32 = np.asarray(w.u0, np.float32)
+    with _solver(w, B.FP32, u0=u32) as s:
+        s.solve(w.T, max_steps=30)
+        u = s.read().astype(np.float64)
+    uo, _, _ = O.solve(_oracle_problem(w), u32.astype(np.float64), w.T, max_steps=30)
+    assert np.mean(np.abs(u - uo)) <= TOL32
+
+
+def test_full_size_burgers_full_solve_conserves_fp64():
+    _say("full size burgers full solve fp64")
+    w = I.burgers_noisy()
+    with _solver(w) as s:
+        m0 = s.stats()["mass"][0]
+        st = s.solve(w.T)
+    assert st["t"] == pytest.approx(w.T, abs=1e-12)
+    assert 40000 < st["nsteps"] < 60000
+    assert abs(st["mass"][0] - m0) <= 1e-13 * np.abs(w.u0).sum() * w.dx
