@@ -1,12 +1,17 @@
-"""Benchmark: cell-updates/s per RK stage of the non-polynomial WENO5 solver on one MI355X.
+"""Benchmark of the non-polynomial WENO5 solver on one MI355X.
 
-Workload (default): 1D Burgers u_t + (u^2/2)_x = 0, periodic on [-1, 1], N = 65536 cells,
-u0 = 0.5 + sin(pi x) + seeded U(-1e-3, 1e-3) noise, global Lax-Friedrichs, SSP-RK3 at CFL 0.5
-to T = 1.5/pi (past shock formation, ~47k steps), RBF-WENO5 with the monotone switch.
-One benchmark "step" = one whole solve from the initial state (state reset from a resident
-device copy, not timed as host traffic).  value = N * 3 * (RK steps) * solves / seconds.
+Default workload (the headline): 1D Burgers u_t + (u^2/2)_x = 0, periodic on [-1, 1],
+N = 65536 cells, u0 = 0.5 + sin(pi x) + seeded U(-1e-3, 1e-3) noise, global Lax-Friedrichs,
+SSP-RK3 at CFL 0.5 to T = 1.5/pi (past shock formation, ~47k RK steps), RBF-WENO5 with the
+monotone switch, float bulk with double eta/switch.  One benchmark "step" is one whole solve
+from the initial state (the state is reset from a resident device copy).
+value = cells * 3 stages * RK steps * solves / wall seconds (cell-updates per RK stage).
 
-Prints one JSON line.  Only one GPU is supported; --gpus N > 1 exits with a message.
+Other workloads (--workload): euler2d (2048^2 four-quadrant 2D Euler to T = 0.25), euler_batch
+(4096 Riemann problems, N in [256, 4096], to T = 0.2), serving (a Poisson trace through the
+continuous-batching loop, compared with one solve at a time).
+
+Prints one JSON line.  Only one GPU: --gpus N > 1 exits with a message.
 """
 from __future__ import annotations
 
@@ -23,10 +28,9 @@ sys.path.insert(0, ROOT)
 import numpy as np  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
-# Algorithmic HBM bytes per cell and RK stage for a scalar state: stage 1 reads u^n and writes
-# u^(1); stages 2 and 3 read u^n, read the stage input and write the output -> (2 + 3 + 3) / 3
-# element accesses per cell-stage.
-ELEM_ACCESSES_PER_CELL_STAGE = 8.0 / 3.0
+# Algorithmic HBM element accesses per cell, component and RK stage: stage 1 reads u^n and
+# writes u^(1); stages 2 and 3 read u^n and the stage input and write the output.
+ACCESSES_PER_CELL_STAGE = 8.0 / 3.0
 
 
 def parse():
@@ -34,111 +38,262 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5, help="timed whole solves")
     ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", choices=["burgers", "euler2d", "euler_batch", "serving"], default="burgers")
     ap.add_argument("--precision", choices=["fp32", "fp64"], default="fp32")
-    ap.add_argument("--n", type=int, default=65536)
+    ap.add_argument("--n", type=int, default=None, help="override the grid size")
+    ap.add_argument("--max-rk-steps", type=int, default=-1,
+                    help="stop each solve after this many RK steps (profiling runs only; not a bench value)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run a 256 MiB device copy (reference for HBM byte counters)")
+    ap.add_argument("--serving-requests", type=int, default=200)
     return ap.parse_args()
+
+
+def _percentiles(x):
+    return {"p50": float(np.percentile(x, 50)), "p99": float(np.percentile(x, 99))}
+
+
+def _time_solves(solver, reset, T, steps, warmup, max_rk, stream):
+    import torch
+    for _ in range(warmup):
+        reset()
+        solver.solve(T, max_rk)
+    torch.cuda.synchronize()
+    lat = []
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    rk = 0
+    for _ in range(steps):
+        a = time.perf_counter()
+        reset()
+        st = solver.solve(T, max_rk)
+        lat.append(time.perf_counter() - a)
+        rk = st["nsteps"]
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return wall, ev0.elapsed_time(ev1) / 1e3, lat, rk
+
+
+def bench_single(args, w, prec, label):
+    """A single grid (1D or 2D) solved from its initial state `steps` times."""
+    import torch
+
+    from paper_1602_00182_amd import binding as B
+    tdt = torch.float32 if prec == B.FP32 else torch.float64
+    u0_dev = torch.tensor(w.u0, dtype=tdt, device="cuda")
+    stream = torch.cuda.Stream()
+    solver = B.Solver(u0_dev, stream=stream.cuda_stream, **B.workload_params(w, prec))
+    wall, gpu_s, lat, rk = _time_solves(solver, lambda: solver.write(u0_dev, 0.0), w.T, args.steps, args.warmup,
+                                        args.max_rk_steps, stream)
+    ncell = w.ncell
+    cell_stages = float(ncell) * 3.0 * rk * args.steps
+    esize = 4 if prec == B.FP32 else 8
+    launches = 3 * rk * args.steps
+    avg_launch = gpu_s / launches
+    bytes_per_launch = ACCESSES_PER_CELL_STAGE * esize * w.ncomp * ncell
+    achieved = bytes_per_launch / avg_launch / 1e9
+    out = {
+        "value": cell_stages / wall,
+        "ms_per_step": 1e3 * wall / args.steps,
+        "latency_s": _percentiles(lat),
+        "rk_steps_per_solve": rk,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": label, "avg_launch_us": avg_launch * 1e6,
+                     "bytes_per_launch": bytes_per_launch},
+    }
+    return out, solver, u0_dev
+
+
+def cpu_baseline(args, w, solver, u0_dev, prec):
+    """The FP64 oracle on the host, one thread, on a bounded sample of the same solve."""
+    import oracle as O
+
+    from paper_1602_00182_amd import binding as B
+    pb = O.Problem(nx=w.nx, ny=w.ny, dim=w.dim, flux=w.flux, ncomp=w.ncomp, bc=w.bc, x0=w.x0, x1=w.x1,
+                   y0=w.y0, y1=w.y1, speed_x=w.speed_x, speed_y=w.speed_y, gamma=w.gamma, cfl=w.cfl,
+                   eps_weno=w.eps_weno, eps_m=w.eps_m, recon=w.recon, switch_mode=w.switch_mode)
+    u_ref = np.asarray(w.u0, np.float32 if prec == B.FP32 else np.float64).astype(np.float64)
+    a = time.perf_counter()
+    u1, t1, _ = O.step(pb, u_ref, w.T)
+    per_step = time.perf_counter() - a
+    k = max(1, int(args.cpu_seconds / max(per_step, 1e-6)))
+    a = time.perf_counter()
+    uo, _, no = O.solve(pb, u1, w.T, t=t1, max_steps=k - 1)
+    el = time.perf_counter() - a + per_step
+    ksteps = no + 1
+    base = {"value": w.ncell * 3.0 * ksteps / el, "unit": "cell-updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"first {ksteps} RK3 steps of the same solve ({w.name}), FP64, one thread"}
+    solver.write(u0_dev, 0.0)
+    solver.solve(w.T, ksteps)
+    ug = solver.read().astype(np.float64)
+    err = {"vs": "FP64 oracle", "rk_steps": ksteps, "l1": float(np.mean(np.abs(ug - uo))),
+           "linf": float(np.max(np.abs(ug - uo)))}
+    return base, err
+
+
+def bench_batch(args, prec):
+    import torch
+
+    from paper_1602_00182_amd import binding as B
+    from paper_1602_00182_amd import inputs as I
+    ws = I.euler_riemann_batch(count=4096 if args.n is None else args.n, seed=3)
+    dt = np.float32 if prec == B.FP32 else np.float64
+    states = [np.asarray(w.u0, dt) for w in ws]
+    stream = torch.cuda.Stream()
+    bt = B.Batch(states, [B.workload_params(w, prec) for w in ws], stream=stream.cuda_stream)
+    T = [w.T for w in ws]
+    # reset = write the packed initial states back (host copy, outside the device work)
+    packed = np.concatenate(states)
+    packed_dev = torch.tensor(packed, device="cuda")
+
+    def reset():
+        B.lib().npweno_write(bt.h, B.ctypes.c_void_p(packed_dev.data_ptr()), 1, 0.0)
+
+    for _ in range(args.warmup):
+        reset()
+        bt.solve(T, args.max_rk_steps)
+    torch.cuda.synchronize()
+    lat = []
+    t0 = time.perf_counter()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    total_cell_stages = 0.0
+    for _ in range(args.steps):
+        a = time.perf_counter()
+        reset()
+        stats, rc = bt.solve(T, args.max_rk_steps)
+        lat.append(time.perf_counter() - a)
+        total_cell_stages += sum(w.nx * 3.0 * s["nsteps"] for w, s in zip(ws, stats))
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    gpu_s = ev0.elapsed_time(ev1) / 1e3
+    max_steps = max(s["nsteps"] for s in stats)
+    esize = 4 if prec == B.FP32 else 8
+    achieved = ACCESSES_PER_CELL_STAGE * esize * 3 * total_cell_stages / gpu_s / 1e9
+    bt.close()
+    return {"value": total_cell_stages / wall, "ms_per_step": 1e3 * wall / args.steps,
+            "latency_s": _percentiles(lat), "instances": len(ws), "cells": int(sum(w.nx for w in ws)),
+            "max_rk_steps": max_steps,
+            "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                         "kernel": "stage1d_kernel<float, Euler, 3> (batched)",
+                         "note": "bytes of all instances / GPU time of the timed region"}}
+
+
+def bench_serving(args, prec):
+    """Replay a Poisson trace in real time through the serving loop, then solve the same
+    requests one at a time on the same GPU."""
+    from paper_1602_00182_amd import binding as B
+    from paper_1602_00182_amd import inputs as I
+    nreq = args.serving_requests
+    trace = I.serving_trace(nreq=nreq, seed=4, nmax=16384)
+    dt = np.float32 if prec == B.FP32 else np.float64
+    work = 0.0
+    srv = B.Server(1 << 30, max_slots=512, precision=prec)
+    pending = list(trace)
+    ids = {}
+    t0 = time.perf_counter()
+    while pending or any(srv.poll(i) is None for i in ids.values()):
+        now = time.perf_counter() - t0
+        while pending and pending[0].arrival <= now:
+            r = pending.pop(0)
+            ids[r.rid] = srv.submit(np.asarray(r.work.u0, dt), r.work.T, **B.workload_params(r.work, prec))
+        srv.pump(16)
+    wall = time.perf_counter() - t0
+    lat, nsteps = [], {}
+    for r in trace:
+        out, st, rc = srv.poll(ids[r.rid])
+        a, b, c = srv.times(ids[r.rid])
+        lat.append(c - (a - (a - t0 - r.arrival)) if False else (c - t0) - r.arrival)
+        nsteps[r.rid] = st["nsteps"]
+        work += r.work.nx * 3.0 * st["nsteps"]
+    srv.close()
+    # one solve at a time, in arrival order (queueing included)
+    t0 = time.perf_counter()
+    lat1 = []
+    for r in trace:
+        now = time.perf_counter() - t0
+        if now < r.arrival:
+            time.sleep(r.arrival - now)
+        with B.Solver(np.asarray(r.work.u0, dt), **B.workload_params(r.work, prec)) as s:
+            s.solve(r.work.T)
+        lat1.append((time.perf_counter() - t0) - r.arrival)
+    wall1 = time.perf_counter() - t0
+    return {"value": work / wall, "requests": nreq, "wall_s": wall, "latency_s": _percentiles(lat),
+            "one_at_a_time": {"value": work / wall1, "wall_s": wall1, "latency_s": _percentiles(lat1)},
+            "offered_rate_req_s": 2000.0, "trace": f"first {nreq} requests of the seed-4 Poisson trace, N capped at 16384"}
 
 
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print(f"bench.py: only one GPU is supported by this build (asked for {max(args.gpus, world)})",
-              file=sys.stderr)
+        print(f"bench.py: this build runs on one GPU only (asked for {max(args.gpus, world)} GPUs)", file=sys.stderr)
         sys.exit(2)
     import torch
 
     from paper_1602_00182_amd import binding as B
     from paper_1602_00182_amd import inputs as I
-
     torch.cuda.set_device(0)
     prec = B.FP32 if args.precision == "fp32" else B.FP64
-    tdt = torch.float32 if prec == B.FP32 else torch.float64
-    w = I.burgers_noisy(n=args.n, seed=2)
-    u0_dev = torch.tensor(w.u0, dtype=tdt, device="cuda")
-    stream = torch.cuda.Stream()  # default priority
-    solver = B.Solver(u0_dev, stream=stream.cuda_stream, **B.workload_params(w, prec))
+    dname = "f32" if prec == B.FP32 else "f64"
+    base = {"unit": "cell-updates/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": dname,
+            "data": "synthetic (seeded)"}
 
-    def one_solve():
-        solver.write(u0_dev, 0.0)
-        st = solver.solve(w.T)
-        return st
+    if args.workload in ("burgers", "euler2d"):
+        if args.workload == "burgers":
+            w = I.burgers_noisy(n=args.n or 65536, seed=2)
+            metric = ("cell-updates/s per RK stage (1D Burgers N=65536, RBF-WENO5 + monotone switch, "
+                      "global LF, SSP-RK3 CFL 0.5 to T=1.5/pi)")
+            label = f"stage1d_kernel<{'float' if prec == B.FP32 else 'double'}, Burgers, 1, 256>"
+        else:
+            w = I.euler2d_quadrants(n=args.n or 2048)
+            metric = "cell-updates/s per RK stage (2D Euler 2048^2 four-quadrant, dimension by dimension, CFL 0.4 to T=0.25)"
+            label = f"stage2d_kernel<{'float' if prec == B.FP32 else 'double'}, Euler, 4, 64, 8>"
+        res, solver, u0_dev = bench_single(args, w, prec, label)
+        out = {"metric": metric, "value": res["value"], **base, "ms_per_step": res["ms_per_step"],
+               "config": {"workload": w.name, "cells": w.ncell, "T": w.T, "cfl": w.cfl,
+                          "rk_steps_per_solve": res["rk_steps_per_solve"], "eta_precision": "f64",
+                          "block": int(os.environ.get("NPW_BLOCK", "256"))},
+               "latency_s": res["latency_s"], "roofline": res["roofline"]}
+        if args.max_rk_steps >= 0:
+            out["note"] = "profiling run: solves stopped after --max-rk-steps; not a benchmark value"
+        if not args.no_cpu_baseline:
+            cb, err = cpu_baseline(args, w, solver, u0_dev, prec)
+            out["cpu_baseline"] = cb
+            out["error_vs_oracle"] = err
+        solver.close()
+    elif args.workload == "euler_batch":
+        res = bench_batch(args, prec)
+        out = {"metric": "cell-updates/s per RK stage (4096 1D Euler Riemann problems, N in [256,4096], T=0.2)",
+               "value": res["value"], **base, "ms_per_step": res["ms_per_step"],
+               "config": {"workload": "euler_riemann_batch_4096", "instances": res["instances"],
+                          "cells": res["cells"], "max_rk_steps": res["max_rk_steps"]},
+               "latency_s": res["latency_s"], "roofline": res["roofline"]}
+    else:
+        res = bench_serving(args, prec)
+        out = {"metric": "cell-updates/s per RK stage, serving (Poisson arrivals, mixed advection/Burgers/Euler)",
+               "value": res["value"], **base, "ms_per_step": None,
+               "config": {"workload": "serving_trace", "requests": res["requests"], "trace": res["trace"]},
+               "latency_s": res["latency_s"], "one_at_a_time": res["one_at_a_time"], "wall_s": res["wall_s"]}
 
-    for _ in range(args.warmup):
-        one_solve()
-    torch.cuda.synchronize()
-    lat = []
-    nsteps = None
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    ev0.record(stream)
-    for _ in range(args.steps):
-        a = time.perf_counter()
-        st = one_solve()
-        lat.append(time.perf_counter() - a)
-        nsteps = st["nsteps"]
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    gpu_ms = ev0.elapsed_time(ev1)
-
-    cell_stages = float(w.nx) * 3.0 * nsteps * args.steps
-    value = cell_stages / wall
-    esize = 4 if prec == B.FP32 else 8
-    launches = 3 * nsteps * args.steps
-    avg_launch_s = (gpu_ms / 1e3) / launches
-    bytes_per_launch = ELEM_ACCESSES_PER_CELL_STAGE * esize * w.nx
-    achieved = bytes_per_launch / avg_launch_s / 1e9
-
-    out = {
-        "metric": "cell-updates/s per RK stage (1D Burgers N=65536, RBF-WENO5 + monotone switch, "
-                  "global LF, SSP-RK3 CFL 0.5 to T=1.5/pi)",
-        "value": value,
-        "unit": "cell-updates/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": 1e3 * wall / args.steps,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32" if prec == B.FP32 else "f64",
-        "data": "synthetic (seeded)",
-        "config": {"workload": "burgers_noisy_N65536", "N": w.nx, "T": w.T, "cfl": w.cfl,
-                   "rk_steps_per_solve": nsteps, "eta_precision": "f64"},
-        "latency_s": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "stage1d_kernel", "avg_launch_us": avg_launch_s * 1e6},
-    }
-
-    if not args.no_cpu_baseline:
-        import oracle as O
-        pb = O.Problem(nx=w.nx, flux=w.flux, cfl=w.cfl, eps_weno=w.eps_weno, eps_m=w.eps_m,
-                       recon=w.recon, switch_mode=w.switch_mode)
-        u_ref = np.asarray(w.u0, np.float32 if prec == B.FP32 else np.float64).astype(np.float64)
-        # size the sample to the time budget from one timed step
-        a = time.perf_counter()
-        u1, t1, _ = O.step(pb, u_ref, w.T)
-        per_step = time.perf_counter() - a
-        k = max(1, int(args.cpu_seconds / max(per_step, 1e-6)))
-        a = time.perf_counter()
-        uo, to, no = O.solve(pb, u1, w.T, t=t1, max_steps=k - 1)
-        el = time.perf_counter() - a + per_step
-        ksteps = no + 1
-        out["cpu_baseline"] = {"value": w.nx * 3.0 * ksteps / el, "unit": "cell-updates/s", "cores": 1,
-                               "kind": "oracle",
-                               "sample": f"first {ksteps} RK3 steps of the same N={w.nx} solve, FP64, one thread"}
-        solver.write(u0_dev, 0.0)
-        solver.solve(w.T, max_steps=ksteps)
-        ug = solver.read().astype(np.float64)
-        out["l1_vs_oracle"] = {"steps": ksteps, "l1": float(np.mean(np.abs(ug - uo))),
-                               "linf": float(np.max(np.abs(ug - uo)))}
-    solver.close()
+    if args.calibrate_copy:
+        n = 64 << 20  # 64 Mi floats = 256 MiB read + 256 MiB written
+        a = torch.empty(n, dtype=torch.float32, device="cuda").uniform_()
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        out["copy_calibration_bytes"] = 4 * n
     print(json.dumps(out), flush=True)
 
 

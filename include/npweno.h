@@ -132,6 +132,53 @@ int npweno_get_stats(const npw_solver* s, npw_stats* stats);
 
 void npweno_destroy(npw_solver* s);
 
+/* ---- Batches ---------------------------------------------------------------------------- */
+/* `count` independent instances that share precision, flux type, ncomp and dim (each may have
+ * its own nx, domain, boundary, cfl, eps_weno, eps_m, recon, switch, speed, gamma).  Their states
+ * are packed back to back in the library's buffers and every RK stage of every instance runs
+ * in one launch of the stage kernel (a tile table maps workgroups to (instance, tile)); each
+ * instance keeps its own alpha, dt, t and error, exactly as if it were solved alone (results
+ * are bit-identical to single-instance solves).  u0[b] points to instance b's initial state
+ * (layout of npweno_create).  The single-instance calls above act on every instance of a batch
+ * with one common t_final; npweno_read copies all states back to back. */
+int npweno_create_batch(const npw_params* params, int32_t count, const void* const* u0, int on_device,
+                        void* hip_stream, npw_solver** out);
+/* Advance instance b towards t_final[b].  max_steps bounds the RK steps launched (< 0: none).
+ * An instance that fails stays at its last good step with its error in per_instance[b].err; the
+ * others continue.  Returns the first error seen, or NPW_OK.  per_instance may be NULL. */
+int npweno_solve_batch(npw_solver* s, const double* t_final, int64_t max_steps, npw_stats* per_instance);
+int npweno_read_instance(const npw_solver* s, int32_t index, void* u_out, int out_on_device);
+int npweno_get_stats_instance(const npw_solver* s, int32_t index, npw_stats* stats);
+int npweno_instance_count(const npw_solver* s);
+
+/* ---- Serving (continuous batching) -------------------------------------------------------- */
+/* A request loop for mixed 1D solves.  All requests share one device arena of
+ * hbm_budget_bytes (split into the three state buffers) and max_slots slots per flux type.
+ * Submitted requests wait in a FIFO queue; npw_server_pump admits the head of the queue as
+ * soon as a slot and a large enough arena range are free, then advances every running request
+ * by `steps` RK steps with one launch of the batched stage kernel per flux type and stage
+ * (their work overlaps on the device), and retires the finished ones.  A request's result is
+ * bit-identical to solving it alone with npweno_create/npweno_solve in the same precision.
+ * Requests never fail one another: a request that becomes non-finite or non-physical is
+ * retired with its error and last good state. */
+int npw_server_create(size_t hbm_budget_bytes, int32_t max_slots, int32_t precision, void* hip_stream,
+                      npw_server** out);
+/* Queue a 1D solve to t_final (params->precision must equal the server's).  The library copies
+ * u0_host.  NPW_EINVAL if the request could never fit in the arena. */
+int npw_server_submit(npw_server* srv, const npw_params* params, const void* u0_host, double t_final,
+                      uint64_t* req_id);
+/* Admit, advance every running request by `steps` RK steps, retire.  Reports the number of
+ * running and queued requests (either pointer may be NULL).  Synchronizes the device. */
+int npw_server_pump(npw_server* srv, int32_t steps, int32_t* n_running, int32_t* n_queued);
+/* NPW_EBUSY until the request finished; then copies its final state (the last good state and
+ * the error code if it failed) and its stats. */
+int npw_server_poll(npw_server* srv, uint64_t req_id, void* u_out_host, npw_stats* stats);
+/* Host steady-clock times (seconds) of submission, admission and completion. */
+int npw_server_times(const npw_server* srv, uint64_t req_id, double* t_submit, double* t_admit, double* t_done);
+/* Drop the stored result of a finished request. */
+int npw_server_release(npw_server* srv, uint64_t req_id);
+void npw_server_destroy(npw_server* srv);
+
 #ifdef __cplusplus
 }
 #endif

@@ -85,8 +85,30 @@ def lib():
         L.npweno_get_stats.argtypes = [_VP, S]
         L.npweno_destroy.argtypes = [_VP]
         L.npweno_destroy.restype = None
+        L.npweno_create_batch.argtypes = [P, ctypes.c_int32, ctypes.POINTER(_VP), ctypes.c_int, _VP,
+                                          ctypes.POINTER(_VP)]
+        L.npweno_solve_batch.argtypes = [_VP, ctypes.POINTER(ctypes.c_double), ctypes.c_int64, S]
+        L.npweno_read_instance.argtypes = [_VP, ctypes.c_int32, _VP, ctypes.c_int]
+        L.npweno_get_stats_instance.argtypes = [_VP, ctypes.c_int32, S]
+        L.npweno_instance_count.argtypes = [_VP]
+        L.npweno_instance_count.restype = ctypes.c_int
+        U64 = ctypes.c_uint64
+        L.npw_server_create.argtypes = [ctypes.c_size_t, ctypes.c_int32, ctypes.c_int32, _VP, ctypes.POINTER(_VP)]
+        L.npw_server_submit.argtypes = [_VP, P, _VP, ctypes.c_double, ctypes.POINTER(U64)]
+        L.npw_server_pump.argtypes = [_VP, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
+                                      ctypes.POINTER(ctypes.c_int32)]
+        L.npw_server_poll.argtypes = [_VP, U64, _VP, S]
+        L.npw_server_times.argtypes = [_VP, U64, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
+                                       ctypes.POINTER(ctypes.c_double)]
+        L.npw_server_release.argtypes = [_VP, U64]
+        L.npw_server_destroy.argtypes = [_VP]
+        L.npw_server_destroy.restype = None
+        for name in ("npw_server_create", "npw_server_submit", "npw_server_pump", "npw_server_poll",
+                     "npw_server_times", "npw_server_release"):
+            getattr(L, name).restype = ctypes.c_int
         for name in ("npweno_create", "npweno_step", "npweno_solve", "npweno_rhs", "npweno_read",
-                     "npweno_write", "npweno_get_stats"):
+                     "npweno_write", "npweno_get_stats", "npweno_create_batch", "npweno_solve_batch",
+                     "npweno_read_instance", "npweno_get_stats_instance"):
             getattr(L, name).restype = ctypes.c_int
         if L.npweno_abi_version() != NPW_ABI_VERSION:
             raise RuntimeError("libnpweno.so ABI version mismatch")
@@ -188,6 +210,135 @@ class Solver:
     def close(self):
         if getattr(self, "h", None):
             lib().npweno_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+class Batch:
+    """Several independent 1D instances stepped together (npweno_create_batch)."""
+
+    def __init__(self, states, params_list, stream=None):
+        if len(states) != len(params_list) or not states:
+            raise ValueError("one parameter set per state")
+        n = len(states)
+        self.params = (Params * n)()
+        for b, kw in enumerate(params_list):
+            self.params[b] = make_params(**kw)
+        self.dtype = np.float64 if self.params[0].precision == FP64 else np.float32
+        self.sizes = [int(p.ncomp * p.nx * (p.ny if p.dim == 2 else 1)) for p in self.params]
+        keep, ptrs, dev = [], (_VP * n)(), 0
+        for b, u in enumerate(states):
+            ptr, d, k = _buf(u, self.dtype)
+            if (k.numel() if d else k.size) != self.sizes[b]:
+                raise ValueError(f"state {b} has the wrong size")
+            ptrs[b] = ptr.value
+            dev = d
+            keep.append(k)
+        h = ctypes.c_void_p()
+        self._stream = _stream_handle(stream)
+        _check(lib().npweno_create_batch(self.params, n, ptrs, dev, self._stream, ctypes.byref(h)),
+               "npweno_create_batch")
+        self.h = h
+        self.count = n
+
+    def solve(self, t_final, max_steps: int = -1, raise_on_error: bool = True):
+        T = (ctypes.c_double * self.count)(*([float(t_final)] * self.count if np.isscalar(t_final) else t_final))
+        st = (Stats * self.count)()
+        rc = lib().npweno_solve_batch(self.h, T, max_steps, st)
+        if rc != OK and raise_on_error:
+            raise NpwError(rc, "npweno_solve_batch")
+        return [x.as_dict() for x in st], rc
+
+    def read(self, b: int, out=None):
+        if out is None:
+            out = np.empty(self.sizes[b], dtype=self.dtype)
+        ptr, dev, keep = _buf(out, self.dtype)
+        _check(lib().npweno_read_instance(self.h, b, ptr, dev), "npweno_read_instance")
+        return keep
+
+    def stats(self, b: int) -> dict:
+        st = Stats()
+        _check(lib().npweno_get_stats_instance(self.h, b, ctypes.byref(st)), "npweno_get_stats_instance")
+        return st.as_dict()
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().npweno_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+class Server:
+    """Continuous-batching request loop (npw_server_*): submit, pump, poll."""
+
+    def __init__(self, hbm_budget_bytes: int, max_slots: int = 256, precision: int = FP32, stream=None):
+        h = ctypes.c_void_p()
+        self.precision = precision
+        self.dtype = np.float64 if precision == FP64 else np.float32
+        _check(lib().npw_server_create(int(hbm_budget_bytes), max_slots, precision, _stream_handle(stream),
+                                       ctypes.byref(h)), "npw_server_create")
+        self.h = h
+        self.sizes = {}
+
+    def submit(self, u0, t_final: float, **params) -> int:
+        params.setdefault("precision", self.precision)
+        p = make_params(**params)
+        a = np.ascontiguousarray(u0, dtype=self.dtype)
+        rid = ctypes.c_uint64()
+        _check(lib().npw_server_submit(self.h, ctypes.byref(p), a.ctypes.data_as(_VP), float(t_final),
+                                       ctypes.byref(rid)), "npw_server_submit")
+        self.sizes[rid.value] = a.size
+        return rid.value
+
+    def pump(self, steps: int = 16):
+        nr, nq = ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().npw_server_pump(self.h, steps, ctypes.byref(nr), ctypes.byref(nq)), "npw_server_pump")
+        return nr.value, nq.value
+
+    def poll(self, rid: int):
+        """None while running; (state, stats, rc) once finished (rc is the request's error code)."""
+        out = np.empty(self.sizes[rid], dtype=self.dtype)
+        st = Stats()
+        rc = lib().npw_server_poll(self.h, rid, out.ctypes.data_as(_VP), ctypes.byref(st))
+        if rc == EBUSY:
+            return None
+        if rc == ENOTFOUND or rc == EINVAL:
+            raise NpwError(rc, "npw_server_poll")
+        return out, st.as_dict(), rc
+
+    def times(self, rid: int):
+        a, b, c = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        lib().npw_server_times(self.h, rid, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c))
+        return a.value, b.value, c.value
+
+    def release(self, rid: int):
+        lib().npw_server_release(self.h, rid)
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().npw_server_destroy(self.h)
             self.h = None
 
     def __del__(self):

@@ -26,6 +26,7 @@ UNITS = [
     ("npw_kernels_f64.hip", ["-ffp-contract=off"]),
     ("npw_kernels_f32.hip", []),
     ("npw_runtime.cpp", ["-x", "hip"]),
+    ("npw_server.cpp", ["-x", "hip"]),
 ]
 
 

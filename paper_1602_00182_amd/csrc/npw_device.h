@@ -14,11 +14,13 @@ namespace npw {
 
 // Ghost-cell index (Section 1 leaves the boundary treatment open): periodic wrap, or a copy of
 // the edge cell (transmissive).
-__device__ __forceinline__ long long ghost_index(long long k, long long n, int bc) {
+// k may lie a few cells outside [0, n) (three ghosts, more only for grids shorter than a tile).
+__device__ __forceinline__ int ghost_index(int k, int n, int bc) {
   if (k >= 0 && k < n) return k;
   if (bc == 0) {
-    long long m = k % n;
-    return m < 0 ? m + n : m;
+    while (k < 0) k += n;
+    while (k >= n) k -= n;
+    return k;
   }
   return k < 0 ? 0 : n - 1;
 }
@@ -224,16 +226,18 @@ __device__ __forceinline__ R spectral_radius(const R* U, R speed, R gamma, int& 
 }
 
 // Time step of the step starting at t (Section 5.1's CFL rule, clipped to the remaining time).
-__device__ __forceinline__ double step_dt(const InstDev* I, double t, double ax, double ay) {
+template <int DIM>
+__device__ __forceinline__ double step_dt(double dt_fixed, double cfl, double dx, double dy, double T, double t,
+                                          double ax, double ay) {
 #pragma clang fp contract(off)
   double dt;
-  if (I->dt_fixed > 0.0)
-    dt = I->dt_fixed;
-  else if (I->dim == 1)
-    dt = I->cfl * I->dx / ax;
+  if (dt_fixed > 0.0)
+    dt = dt_fixed;
+  else if constexpr (DIM == 1)
+    dt = cfl * dx / ax;
   else
-    dt = I->cfl / (ax / I->dx + ay / I->dy);
-  double rem = I->T - t;
+    dt = cfl / (ax / dx + ay / dy);
+  double rem = T - t;
   if (dt > rem) dt = rem;
   return dt;
 }
@@ -243,14 +247,46 @@ __device__ __forceinline__ unsigned long long double_to_bits(double d) {
   return (unsigned long long)__double_as_longlong(d);
 }
 
-// Max of a non-negative value over the wavefront (64 lanes), on the bit pattern.
-__device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) {
-    unsigned long long o = __shfl_xor(v, off, 64);
-    v = o > v ? o : v;
+// Max of a non-negative value over the wavefront with DPP moves (rows of 16 lanes, then the
+// row broadcasts); lanes without a source read 0, the identity for non-negative values.  Every
+// lane gets the result of lane 63.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ unsigned dpp_take(unsigned v) {
+  return (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, ROWS, 0xf, true);
+}
+template <int CTRL, int ROWS>
+__device__ __forceinline__ float dpp_max_step(float v) {
+  return fmaxf(v, __uint_as_float(dpp_take<CTRL, ROWS>(__float_as_uint(v))));
+}
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_max_step(double v) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const unsigned lo = dpp_take<CTRL, ROWS>((unsigned)b), hi = dpp_take<CTRL, ROWS>((unsigned)(b >> 32));
+  return fmax(v, __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo)));
+}
+template <typename R>
+__device__ __forceinline__ R wave_max_nonneg(R v) {
+  v = dpp_max_step<0x111, 0xf>(v);  // row_shr:1
+  v = dpp_max_step<0x112, 0xf>(v);  // row_shr:2
+  v = dpp_max_step<0x114, 0xf>(v);  // row_shr:4
+  v = dpp_max_step<0x118, 0xf>(v);  // row_shr:8  -> lane 15 of each row holds the row max
+  v = dpp_max_step<0x142, 0xa>(v);  // row_bcast:15 into rows 1 and 3
+  v = dpp_max_step<0x143, 0xc>(v);  // row_bcast:31 into rows 2 and 3 -> lane 63 holds the max
+  if constexpr (sizeof(R) == 4) {
+    return __uint_as_float((unsigned)__builtin_amdgcn_readlane((int)__float_as_uint(v), 63));
+  } else {
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, 63);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), 63);
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
   }
-  return v;
+}
+
+// alpha of (slot, dir) for every lane: the max of the kSpread entries (one per lane, then DPP).
+__device__ __forceinline__ unsigned long long spread_read(const unsigned long long* spread, int slot, int dir) {
+  const int lane = threadIdx.x & 63;
+  const unsigned long long v = spread[((slot * 2 + dir) * kSpread + lane) * kSpreadStride];
+  return double_to_bits(wave_max_nonneg(bits_to_double(v)));
 }
 
 }  // namespace npw

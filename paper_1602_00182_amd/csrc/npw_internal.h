@@ -16,7 +16,7 @@ struct Ctl {
   double dt;     // step size (0 when the instance is idle)
   long long n;   // index of the step in progress (= steps completed before it)
   int active;    // 1 while this step is being taken
-  int pad;
+  int home;      // ctl[0]: which ping-pong buffer (0/1) holds u^n
 };
 
 // One grid instance.  The static part is written by the host; the dynamic part only by kernels
@@ -25,6 +25,7 @@ struct InstDev {
   long long off;  // element offset of the instance's state block in every state buffer
   long long nx, ny;
   double dx, dy, cfl, dt_fixed, T, tol;
+  double inv_dx, inv_dy;  // float bulk multiplies by these instead of dividing
   double speed_x, speed_y, gamma, eps_weno, eps_m;
   int bc, recon, sw, dim;
   // dynamic
@@ -36,32 +37,55 @@ struct InstDev {
   int err_stage;  // stage that detected it
   long long err_n;
   double err_t;
+  int err_home;   // buffer holding the last good state
+  int pad2;
   double mass[4];  // per-component sums of the state (filled by the stats kernel)
 };
 
+// One workgroup's share of an instance.  The instance's geometry is repeated here so that the
+// state loads can be issued without first reading the instance record.
 struct Tile {
   int inst;
-  int pad;
-  long long start;  // first owned cell (1D: cell index; 2D: unused)
+  int bc;
+  long long start;  // first owned cell
+  long long nx;     // cells of the instance
+  long long off;    // element offset of the instance's state block
 };
 
 struct StageArgs {
   InstDev* inst;
-  const Tile* tiles;
+  const Tile* tiles;      // null: a single instance, tile b starts at cell b*(BS-2)
   int ntiles;             // tile count (and grid size) when ntiles_dev is null
   const int* ntiles_dev;  // optional device-resident tile count (serving)
+  long long nx;           // single instance: cells (x)
+  long long ny;           // 2D: cells along y
+  int bc;                 // single instance: boundary kind
+  int par;                // u^n of every instance stepped by this launch lives in P[par]
   void* P0;  // ping-pong buffer 0
   void* P1;  // ping-pong buffer 1
   void* C;   // u^(2) buffer
   void* out; // rhs mode: destination of L(u)
   int stage; // 1, 2, 3: SSP-RK3 stage; 0: evaluate L(u^n) into out
+  // Single-grid solvers spread each alpha slot over kSpread cache lines so that hundreds of
+  // workgroups do not queue on one atomic: entry (slot, dir, k) lives at
+  // spread[((slot * 2 + dir) * kSpread + k) * kSpreadStride].  Null for batches (they use
+  // InstDev.alpha directly, with few workgroups per instance).
+  unsigned long long* spread;
 };
+
+constexpr int kSpread = 64;
+constexpr int kSpreadStride = 16;  // 128 bytes between entries
+constexpr int kSpreadWords = 3 * 2 * kSpread * kSpreadStride;
 
 // Launchers implemented in the kernel translation units (one per bulk precision).
 hipError_t launch_stage_f64(int flux, int ncomp, int block, const StageArgs& a, hipStream_t s);
 hipError_t launch_stage_f32(int flux, int ncomp, int block, const StageArgs& a, hipStream_t s);
 // Recompute alpha slot 0, finiteness/physicality checks and the per-component sums of u^n.
-hipError_t launch_init_f64(int flux, int ncomp, InstDev* inst, int ninst, void* P0, void* P1, hipStream_t s);
-hipError_t launch_init_f32(int flux, int ncomp, InstDev* inst, int ninst, void* P0, void* P1, hipStream_t s);
+hipError_t launch_stage2d_f64(int flux, int ncomp, const StageArgs& a, hipStream_t s);
+hipError_t launch_stage2d_f32(int flux, int ncomp, const StageArgs& a, hipStream_t s);
+hipError_t launch_init_f64(int flux, int ncomp, InstDev* inst, int ninst, void* P0, void* P1,
+                           unsigned long long* spread, hipStream_t s);
+hipError_t launch_init_f32(int flux, int ncomp, InstDev* inst, int ninst, void* P0, void* P1,
+                           unsigned long long* spread, hipStream_t s);
 
 }  // namespace npw

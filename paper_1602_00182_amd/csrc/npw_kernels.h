@@ -34,101 +34,126 @@ __device__ __forceinline__ void stage1d_tile(const StageArgs& a, const Tile tile
   __shared__ unsigned long long s_red[BS / 64];
   __shared__ int s_bad[BS / 64];
 
-  InstDev* I = a.inst + tile.inst;
   const int tid = threadIdx.x;
   const int stage = a.stage;
-  const bool lead = (tile.start == 0 && tid == 0);
+  const int start = (int)tile.start, nx = (int)tile.nx;
+  const long long off = tile.off;
+  const int bc = tile.bc;
+  const int par = a.par;
 
-  if (I->err) return;
+  // ---- issue the state loads first: they only depend on the launch and the tile ------------
+  R* un = reinterpret_cast<R*>(par ? a.P1 : a.P0) + off;
+  R* uo = reinterpret_cast<R*>(par ? a.P0 : a.P1) + off;
+  R* u2 = reinterpret_cast<R*>(a.C) + off;
+  const R* src = (stage == 0 || stage == 1) ? un : (stage == 2 ? uo : u2);
+  R* dst = stage == 0 ? reinterpret_cast<R*>(a.out) + off : (stage == 2 ? u2 : uo);
+  const int cell = start - 1 + tid;
+  const bool owned = (tid >= 1 && tid <= BS - 2 && cell < nx);
+  R ld0[M], ld1[M], upt[M];
+  {
+    const int g0 = ghost_index(start - 3 + tid, nx, bc);
+#pragma unroll
+    for (int c = 0; c < M; ++c) ld0[c] = src[c * nx + g0];
+    if (tid < W - BS) {
+      const int g1 = ghost_index(start - 3 + BS + tid, nx, bc);
+#pragma unroll
+      for (int c = 0; c < M; ++c) ld1[c] = src[c * nx + g1];
+    }
+    if ((stage == 2 || stage == 3) && owned) {
+#pragma unroll
+      for (int c = 0; c < M; ++c) upt[c] = un[c * nx + cell];
+    }
+  }
 
   // ---- step control (see Ctl): read the word of the previous stage, write our own ---------
+  InstDev* I = a.inst + tile.inst;
+  unsigned long long* sp = a.spread;
+  const bool lead = (start == 0 && tid == 0);
+  const bool lead_wave = (start == 0 && tid < 64);
+  const int err = I->err;
+  const Ctl c0 = I->ctl[0], c1 = I->ctl[1], c2 = I->ctl[2];
+  const int slot_in = stage == 0 ? 0 : stage - 1;
+  const unsigned long long alpha_bits = sp ? spread_read(sp, slot_in, 0) : I->alpha[slot_in][0];
+  const double T = I->T, tol = I->tol;
+  const double dt_fixed = I->dt_fixed, cfl = I->cfl, dxd = I->dx;
+  // zero an alpha slot before the kernel that accumulates into it runs
+  auto zero_slot = [&](int slot) {
+    if (sp) {
+      if (lead_wave) {
+        sp[((slot * 2 + 0) * kSpread + tid) * kSpreadStride] = 0ull;
+        sp[((slot * 2 + 1) * kSpread + tid) * kSpreadStride] = 0ull;
+      }
+    } else if (lead) {
+      I->alpha[slot][0] = 0ull;
+      I->alpha[slot][1] = 0ull;
+    }
+  };
+  if (err) return;
   double t, dt = 0.0;
   long long n;
-  unsigned long long alpha_bits;
   if (stage == 1) {
-    t = I->ctl[0].t;
-    n = I->ctl[0].n;
-    const bool active = (I->T - t) > I->tol;
-    if (active) dt = step_dt(I, t, bits_to_double(I->alpha[0][0]), bits_to_double(I->alpha[0][1]));
+    t = c0.t;
+    n = c0.n;
+    const bool active = (T - t) > tol;
+    if (active) dt = step_dt<1>(dt_fixed, cfl, dxd, 0.0, T, t, bits_to_double(alpha_bits), 0.0);
     if (lead) {
       Ctl c;
       c.t = t;
       c.dt = dt;
       c.n = n;
       c.active = active ? 1 : 0;
-      c.pad = 0;
+      c.home = par;
       I->ctl[1] = c;
-      if (active) {
-        I->alpha[2][0] = 0ull;
-        I->alpha[2][1] = 0ull;
-      }
     }
     if (!active) return;
-    alpha_bits = I->alpha[0][0];
+    zero_slot(2);
   } else if (stage == 2) {
-    const Ctl c = I->ctl[1];
-    if (lead) {
-      I->ctl[2] = c;
-      if (c.active) {
-        I->alpha[0][0] = 0ull;
-        I->alpha[0][1] = 0ull;
-      }
-    }
-    if (!c.active) return;
-    t = c.t;
-    dt = c.dt;
-    n = c.n;
-    alpha_bits = I->alpha[1][0];
+    if (lead) I->ctl[2] = c1;
+    if (!c1.active) return;
+    zero_slot(0);
+    t = c1.t;
+    dt = c1.dt;
+    n = c1.n;
   } else if (stage == 3) {
-    const Ctl c = I->ctl[2];
-    if (!c.active) return;
+    if (!c2.active) return;
     if (lead) {
       Ctl d;
-      d.t = c.t + c.dt;
+      d.t = c2.t + c2.dt;
       d.dt = 0.0;
-      d.n = c.n + 1;
+      d.n = c2.n + 1;
       d.active = 0;
-      d.pad = 0;
+      d.home = par ^ 1;
       I->ctl[0] = d;
-      I->alpha[1][0] = 0ull;
-      I->alpha[1][1] = 0ull;
     }
-    t = c.t;
-    dt = c.dt;
-    n = c.n;
-    alpha_bits = I->alpha[2][0];
+    zero_slot(1);
+    t = c2.t;
+    dt = c2.dt;
+    n = c2.n;
   } else {
-    t = I->ctl[0].t;
-    n = I->ctl[0].n;
-    alpha_bits = I->alpha[0][0];
+    t = c0.t;
+    n = c0.n;
   }
   const R alpha = R(bits_to_double(alpha_bits));
   const R rdt = R(dt);
-
-  // ---- buffers: u^n lives in P[n & 1]; u^(1) and u^(n+1) in the other; u^(2) in C ----------
-  const long long off = I->off, nx = I->nx;
-  R* un = reinterpret_cast<R*>((n & 1) ? a.P1 : a.P0) + off;
-  R* uo = reinterpret_cast<R*>((n & 1) ? a.P0 : a.P1) + off;
-  R* u2 = reinterpret_cast<R*>(a.C) + off;
-  const R* src = (stage == 0 || stage == 1) ? un : (stage == 2 ? uo : u2);
-  R* dst = stage == 0 ? reinterpret_cast<R*>(a.out) + off : (stage == 2 ? u2 : uo);
-
-  const int bc = I->bc;
-  const long long start = tile.start;
   const bool use_eta = (I->recon == NPW_RBF_WENO5);
   const bool use_switch = use_eta && (I->sw == NPW_SWITCH_MONOTONE);
   const double eps_m = I->eps_m;
   const R eps = R(I->eps_weno);
   const R speed = R(I->speed_x), gamma = R(I->gamma);
+  const R dx = R(dxd);
+  const R inv_dx = R(I->inv_dx);
 
-  // ---- load ------------------------------------------------------------------------------
-  for (int idx = tid; idx < W; idx += BS) {
-    const long long g = ghost_index(start - 3 + idx, nx, bc);
+  // ---- stage input into LDS ----------------------------------------------------------------
+#pragma unroll
+  for (int c = 0; c < M; ++c) {
+    s_u[c][tid] = ld0[c];
+    if constexpr (!kExact) s_d[c][tid] = double(ld0[c]);
+  }
+  if (tid < W - BS) {
 #pragma unroll
     for (int c = 0; c < M; ++c) {
-      R v = src[c * nx + g];
-      s_u[c][idx] = v;
-      if constexpr (!kExact) s_d[c][idx] = double(v);
+      s_u[c][BS + tid] = ld1[c];
+      if constexpr (!kExact) s_d[c][BS + tid] = double(ld1[c]);
     }
   }
   __syncthreads();
@@ -189,47 +214,37 @@ __device__ __forceinline__ void stage1d_tile(const StageArgs& a, const Tile tile
   }
   __syncthreads();
   // ---- update of the owned cells (tid = 1 .. BS-2) ---------------------------------------------
-  const long long cell = start - 1 + tid;
-  const bool owned = (tid >= 1 && tid <= BS - 2 && cell < nx);
-  unsigned long long amax = 0ull;
+  R amax = R(0);
   int bad = 0;
   if (owned) {
-    const R dx = R(I->dx);
     R unew[M];
 #pragma unroll
     for (int c = 0; c < M; ++c) {
-      const R L = -(s_F[c][tid] - s_F[c][tid - 1]) / dx;
+      R L;
+      if constexpr (kExact)
+        L = -(s_F[c][tid] - s_F[c][tid - 1]) / dx;
+      else
+        L = (s_F[c][tid - 1] - s_F[c][tid]) * inv_dx;
       if (stage == 0) {
         unew[c] = L;
       } else if (stage == 1) {
         unew[c] = s_u[c][tid + 2] + rdt * L;
       } else if (stage == 2) {
-        const R u0 = un[c * nx + cell];
-        unew[c] = R(0.75) * u0 + R(0.25) * (s_u[c][tid + 2] + rdt * L);
+        unew[c] = R(0.75) * upt[c] + R(0.25) * (s_u[c][tid + 2] + rdt * L);
       } else {
-        const R u0 = un[c * nx + cell];
-        unew[c] = R(1.0 / 3.0) * u0 + R(2.0 / 3.0) * (s_u[c][tid + 2] + rdt * L);
+        unew[c] = R(1.0 / 3.0) * upt[c] + R(2.0 / 3.0) * (s_u[c][tid + 2] + rdt * L);
       }
       dst[c * nx + cell] = unew[c];
     }
-    if (stage != 0) {
-      const R sr = spectral_radius<R, FLUX, M, 0>(unew, speed, gamma, bad);
-      amax = double_to_bits(double(sr));
-    }
+    if (stage != 0) amax = spectral_radius<R, FLUX, M, 0>(unew, speed, gamma, bad);
   }
   if (stage == 0) return;
   // ---- epilogue: alpha of the new state and validity -------------------------------------
-  amax = wave_max_u64(amax);
-  const int anybad = __any(bad != 0) ? 1 : 0;
-  int worst = bad;
-#pragma unroll
-  for (int off2 = 32; off2 > 0; off2 >>= 1) {
-    int o = __shfl_xor(worst, off2, 64);
-    worst = o > worst ? o : worst;
-  }
+  amax = wave_max_nonneg(amax);
+  const bool bad2 = __any(bad == 2), bad1 = __any(bad == 1);
   if ((tid & 63) == 0) {
-    s_red[tid >> 6] = amax;
-    s_bad[tid >> 6] = anybad ? worst : 0;
+    s_red[tid >> 6] = double_to_bits(double(amax));
+    s_bad[tid >> 6] = bad2 ? 2 : (bad1 ? 1 : 0);
   }
   __syncthreads();
   if (tid == 0) {
@@ -247,9 +262,10 @@ __device__ __forceinline__ void stage1d_tile(const StageArgs& a, const Tile tile
         I->err_stage = stage;
         I->err_n = n;
         I->err_t = t;
+        I->err_home = par;
       }
     } else {
-      atomicMax(&I->alpha[slot][0], m);
+      atomicMax(sp ? &sp[((slot * 2 + 0) * kSpread + blockIdx.x % kSpread) * kSpreadStride] : &I->alpha[slot][0], m);
     }
   }
 }
@@ -258,6 +274,16 @@ __device__ __forceinline__ void stage1d_tile(const StageArgs& a, const Tile tile
 // table is shared with a serving loop, so captured graphs stay valid as instances come and go.
 template <typename R, int FLUX, int M, int BS>
 __global__ __launch_bounds__(BS) void stage1d_kernel(StageArgs a) {
+  if (a.tiles == nullptr) {  // single instance: tiles follow from the block index
+    Tile t;
+    t.inst = 0;
+    t.bc = a.bc;
+    t.start = (long long)blockIdx.x * (BS - 2);
+    t.nx = a.nx;
+    t.off = 0;
+    stage1d_tile<R, FLUX, M, BS>(a, t);
+    return;
+  }
   const int nt = a.ntiles_dev ? *a.ntiles_dev : a.ntiles;
   for (int ti = blockIdx.x; ti < nt; ti += gridDim.x) {
     stage1d_tile<R, FLUX, M, BS>(a, a.tiles[ti]);
@@ -268,11 +294,11 @@ __global__ __launch_bounds__(BS) void stage1d_kernel(StageArgs a) {
 // State check of u^n for every instance (one workgroup per instance): alpha slot 0, validity
 // and the per-component sums (FP64, fixed order, so repeated calls agree bit for bit).
 template <typename R, int FLUX, int M>
-__global__ __launch_bounds__(256) void init_kernel(InstDev* inst, void* P0, void* P1) {
+__global__ __launch_bounds__(256) void init_kernel(InstDev* inst, void* P0, void* P1, unsigned long long* spread) {
   InstDev* I = inst + blockIdx.x;
   const int tid = threadIdx.x;
   const long long n = I->ctl[0].n, nx = I->nx, ncell = I->nx * (I->dim == 2 ? I->ny : 1);
-  const R* u = reinterpret_cast<const R*>((n & 1) ? P1 : P0) + I->off;
+  const R* u = reinterpret_cast<const R*>(I->ctl[0].home ? P1 : P0) + I->off;
   const R speed = R(I->speed_x), gamma = R(I->gamma);
   (void)nx;
   unsigned long long ax = 0ull, ay = 0ull;
@@ -311,6 +337,10 @@ __global__ __launch_bounds__(256) void init_kernel(InstDev* inst, void* P0, void
   s_ay[tid] = ay;
   s_b[tid] = bad;
   __syncthreads();
+  if (spread) {  // single grid: slot 0 holds alpha in entry 0, every other entry starts at zero
+    for (int k = tid; k < 3 * 2 * kSpread; k += 256) spread[k * kSpreadStride] = 0ull;
+  }
+  __syncthreads();
   if (tid == 0) {
     double tot[M];
     unsigned long long mx = 0ull, my = 0ull;
@@ -328,11 +358,16 @@ __global__ __launch_bounds__(256) void init_kernel(InstDev* inst, void* P0, void
     for (int c = 0; c < 4; ++c) I->mass[c] = c < M ? tot[c] * area : 0.0;
     I->alpha[0][0] = mx;
     I->alpha[0][1] = my;
+    if (spread) {
+      spread[(0 * kSpread + 0) * kSpreadStride] = mx;
+      spread[(1 * kSpread + 0) * kSpreadStride] = my;
+    }
     if (w) {
       I->err = w == 2 ? NPW_ENONPHYSICAL : NPW_ENONFINITE;
       I->err_stage = 0;
       I->err_n = n;
       I->err_t = I->ctl[0].t;
+      I->err_home = I->ctl[0].home;
     }
   }
 }

@@ -1,0 +1,332 @@
+// npw_kernels2d.h -- fused SSP-RK3 stage kernel for 2D grids, dimension by dimension.
+//
+// Section 7 (eq. 2DIntegral) with one midpoint quadrature point per face: every row is
+// reconstructed along x with the 1D scheme and every column along y, and
+//   L_ij = -(F_{i+1/2,j} - F_{i-1/2,j}) / dx - (G_{i,j+1/2} - G_{i,j-1/2}) / dy,
+// with one global Lax-Friedrichs alpha per direction.  One workgroup owns a TX x TY tile; it
+// stages the tile with a three-cell halo in LDS, runs the x sweep (flags, eta, reconstruction,
+// flux) over the TY rows, accumulates -dF/dx, runs the same sweep over the TX columns along y,
+// and applies the stage update.  The epilogue reduces alpha_x and alpha_y of the new state.
+#pragma once
+#include <type_traits>
+
+#include "../../include/npweno.h"
+#include "npw_device.h"
+
+namespace npw {
+
+template <typename R, int FLUX, int M, int TX, int TY>
+__global__ __launch_bounds__(256) void stage2d_kernel(StageArgs a) {
+  constexpr int BS = 256;
+  constexpr bool kExact = std::is_same<R, double>::value;
+  constexpr int WX = TX + 6, WY = TY + 6;                          // staged cells per row / column
+  constexpr int NC = (TX + 2) * TY > TX * (TY + 2) ? (TX + 2) * TY : TX * (TY + 2);  // sweep cells
+  __shared__ R s_u[M][WY][WX];
+  __shared__ unsigned char s_flag[M][NC];
+  __shared__ R s_eta[M][NC];
+  __shared__ R s_vp[M][NC];
+  __shared__ R s_F[M][NC];
+  __shared__ R s_L[M][TY][TX];
+  static_assert(TX % 1 == 0 && TY % 1 == 0 && NC >= (TX + 2) * TY, "sweep buffers");
+  __shared__ unsigned long long s_red[2][BS / 64];
+  __shared__ int s_bad[BS / 64];
+
+  const int tid = threadIdx.x;
+  const int stage = a.stage;
+  const int nx = (int)a.nx, ny = (int)a.ny;
+  const int i0 = blockIdx.x * TX, j0 = blockIdx.y * TY;
+  const int bc = a.bc;
+  const int par = a.par;
+  const long long ncell = (long long)nx * ny;
+
+  R* un = reinterpret_cast<R*>(par ? a.P1 : a.P0);
+  R* uo = reinterpret_cast<R*>(par ? a.P0 : a.P1);
+  R* u2 = reinterpret_cast<R*>(a.C);
+  const R* src = (stage == 0 || stage == 1) ? un : (stage == 2 ? uo : u2);
+  R* dst = stage == 0 ? reinterpret_cast<R*>(a.out) : (stage == 2 ? u2 : uo);
+
+  // ---- issue the state loads (tile + halo, every component) -------------------------------
+  constexpr int NLD = (WX * WY + BS - 1) / BS;
+  R ld[NLD][M];
+#pragma unroll
+  for (int k = 0; k < NLD; ++k) {
+    const int idx = tid + k * BS;
+    if (idx < WX * WY) {
+      const int gy = ghost_index(j0 - 3 + idx / WX, ny, bc), gx = ghost_index(i0 - 3 + idx % WX, nx, bc);
+#pragma unroll
+      for (int c = 0; c < M; ++c) ld[k][c] = src[c * ncell + (long long)gy * nx + gx];
+    }
+  }
+  constexpr int NOWN = (TX * TY + BS - 1) / BS;
+  R upt[NOWN][M];
+  if (stage == 2 || stage == 3) {
+#pragma unroll
+    for (int k = 0; k < NOWN; ++k) {
+      const int o = tid + k * BS;
+      const int x = i0 + o % TX, y = j0 + o / TX;
+      if (o < TX * TY && x < nx && y < ny) {
+#pragma unroll
+        for (int c = 0; c < M; ++c) upt[k][c] = un[c * ncell + (long long)y * nx + x];
+      }
+    }
+  }
+
+  // ---- step control (same protocol as the 1D kernel; the lead is block (0, 0)) -------------
+  InstDev* I = a.inst;
+  unsigned long long* sp = a.spread;
+  const bool first_block = (blockIdx.x == 0 && blockIdx.y == 0);
+  const bool lead = first_block && tid == 0;
+  const int err = I->err;
+  const Ctl c0 = I->ctl[0], c1 = I->ctl[1], c2 = I->ctl[2];
+  const int slot_in = stage == 0 ? 0 : stage - 1;
+  const unsigned long long ax_bits = sp ? spread_read(sp, slot_in, 0) : I->alpha[slot_in][0];
+  const unsigned long long ay_bits = sp ? spread_read(sp, slot_in, 1) : I->alpha[slot_in][1];
+  const double T = I->T, tol = I->tol;
+  const double dt_fixed = I->dt_fixed, cfl = I->cfl, dxd = I->dx, dyd = I->dy;
+  auto zero_slot = [&](int slot) {
+    if (sp) {
+      if (first_block && tid < 64) {
+        sp[((slot * 2 + 0) * kSpread + tid) * kSpreadStride] = 0ull;
+        sp[((slot * 2 + 1) * kSpread + tid) * kSpreadStride] = 0ull;
+      }
+    } else if (lead) {
+      I->alpha[slot][0] = 0ull;
+      I->alpha[slot][1] = 0ull;
+    }
+  };
+  if (err) return;
+  double t, dt = 0.0;
+  long long n;
+  if (stage == 1) {
+    t = c0.t;
+    n = c0.n;
+    const bool active = (T - t) > tol;
+    if (active) dt = step_dt<2>(dt_fixed, cfl, dxd, dyd, T, t, bits_to_double(ax_bits), bits_to_double(ay_bits));
+    if (lead) {
+      Ctl c;
+      c.t = t;
+      c.dt = dt;
+      c.n = n;
+      c.active = active ? 1 : 0;
+      c.home = par;
+      I->ctl[1] = c;
+    }
+    if (!active) return;
+    zero_slot(2);
+  } else if (stage == 2) {
+    if (lead) I->ctl[2] = c1;
+    if (!c1.active) return;
+    zero_slot(0);
+    t = c1.t;
+    dt = c1.dt;
+    n = c1.n;
+  } else if (stage == 3) {
+    if (!c2.active) return;
+    if (lead) {
+      Ctl d;
+      d.t = c2.t + c2.dt;
+      d.dt = 0.0;
+      d.n = c2.n + 1;
+      d.active = 0;
+      d.home = par ^ 1;
+      I->ctl[0] = d;
+    }
+    zero_slot(1);
+    t = c2.t;
+    dt = c2.dt;
+    n = c2.n;
+  } else {
+    t = c0.t;
+    n = c0.n;
+  }
+  const R alpha_x = R(bits_to_double(ax_bits)), alpha_y = R(bits_to_double(ay_bits));
+  const R rdt = R(dt);
+  const bool use_eta = (I->recon == NPW_RBF_WENO5);
+  const bool use_switch = use_eta && (I->sw == NPW_SWITCH_MONOTONE);
+  const double eps_m = I->eps_m;
+  const R eps = R(I->eps_weno);
+  const R speed_x = R(I->speed_x), speed_y = R(I->speed_y), gamma = R(I->gamma);
+  const R dx = R(dxd), dy = R(dyd), inv_dx = R(I->inv_dx), inv_dy = R(I->inv_dy);
+
+#pragma unroll
+  for (int k = 0; k < NLD; ++k) {
+    const int idx = tid + k * BS;
+    if (idx < WX * WY) {
+#pragma unroll
+      for (int c = 0; c < M; ++c) s_u[c][idx / WX][idx % WX] = ld[k][c];
+    }
+  }
+  __syncthreads();
+
+  // One sweep direction.  Cells along the sweep are addressed by (line, pos): pos runs over
+  // -1..LEN (LEN = TX for x, TY for y), line over the other tile extent.  U(c, line, q) is the
+  // staged average at sweep offset q (q = pos + 3 is the LDS coordinate along the sweep).
+  auto sweep = [&](auto dir_tag) {
+    constexpr int DIR = decltype(dir_tag)::value;
+    constexpr int LEN = DIR == 0 ? TX : TY;
+    constexpr int LINES = DIR == 0 ? TY : TX;
+    constexpr int NPOS = LEN + 2;  // cells -1 .. LEN
+    auto U = [&](int c, int line, int q) -> R {
+      return DIR == 0 ? s_u[c][line + 3][q] : s_u[c][q][line + 3];
+    };
+    // flags of cells -1..LEN (window centred on the cell)
+    if (use_switch) {
+      for (int w = tid; w < NPOS * LINES; w += BS) {
+        const int line = w / NPOS, pos = w % NPOS - 1, q = pos + 3;
+#pragma unroll
+        for (int c = 0; c < M; ++c)
+          s_flag[c][w] = (unsigned char)monotone_flag(double(U(c, line, q - 1)), double(U(c, line, q)),
+                                                      double(U(c, line, q + 1)));
+      }
+    }
+    __syncthreads();
+    // eta of the interfaces pos+1/2, pos = -1..LEN-1 (stored at the index of cell pos)
+    for (int w = tid; w < NPOS * LINES; w += BS) {
+      const int line = w / NPOS, pos = w % NPOS - 1, q = pos + 3;
+      if (pos > LEN - 1) continue;
+#pragma unroll
+      for (int c = 0; c < M; ++c) {
+        double e = 0.0;
+        if (use_eta) {
+          e = eta_ratio(double(U(c, line, q - 1)), double(U(c, line, q)), double(U(c, line, q + 1)),
+                        double(U(c, line, q + 2)), eps_m);
+          if (use_switch && (s_flag[c][w] | s_flag[c][w + 1])) e = 0.0;
+        }
+        s_eta[c][w] = R(e);
+      }
+    }
+    __syncthreads();
+    // v^- (kept in s_F for the moment) and v^+ of cells -1..LEN
+    for (int w = tid; w < NPOS * LINES; w += BS) {
+      const int line = w / NPOS, pos = w % NPOS - 1, q = pos + 3;
+#pragma unroll
+      for (int c = 0; c < M; ++c) {
+        const R eta_r = pos <= LEN - 1 ? s_eta[c][w] : R(0);
+        const R eta_l = pos >= 0 ? s_eta[c][w - 1] : R(0);
+        R vm = R(0), vp = R(0);
+        if constexpr (kExact)
+          weno_pair_exact(U(c, line, q - 2), U(c, line, q - 1), U(c, line, q), U(c, line, q + 1), U(c, line, q + 2),
+                          eta_r, eta_l, eps, pos <= LEN - 1, pos >= 0, vm, vp);
+        else
+          weno_pair_fast(U(c, line, q - 2), U(c, line, q - 1), U(c, line, q), U(c, line, q + 1), U(c, line, q + 2),
+                         eta_r, eta_l, eps, pos <= LEN - 1, pos >= 0, vm, vp);
+        s_F[c][w] = vm;
+        s_vp[c][w] = vp;
+      }
+    }
+    __syncthreads();
+    // flux at pos+1/2 from v^-(pos) and v^+(pos+1), written over v^-(pos) by the same thread
+    for (int w = tid; w < NPOS * LINES; w += BS) {
+      const int pos = w % NPOS - 1;
+      if (pos > LEN - 1) continue;
+      R A[M], B[M], H[M];
+#pragma unroll
+      for (int c = 0; c < M; ++c) {
+        A[c] = s_F[c][w];
+        B[c] = s_vp[c][w + 1];
+      }
+      if constexpr (DIR == 0)
+        lf_flux<R, FLUX, M, 0>(A, B, alpha_x, speed_x, gamma, H);
+      else
+        lf_flux<R, FLUX, M, 1>(A, B, alpha_y, speed_y, gamma, H);
+#pragma unroll
+      for (int c = 0; c < M; ++c) s_F[c][w] = H[c];
+    }
+    __syncthreads();
+    // flux difference into the owned cells
+    for (int o = tid; o < TX * TY; o += BS) {
+      const int x = o % TX, y = o / TX;
+      const int line = DIR == 0 ? y : x, pos = DIR == 0 ? x : y;
+      const int w = line * NPOS + pos + 1;  // index of cell pos: interface pos+1/2
+#pragma unroll
+      for (int c = 0; c < M; ++c) {
+        const R Fp = s_F[c][w], Fm = s_F[c][w - 1];
+        if constexpr (DIR == 0) {
+          if constexpr (kExact)
+            s_L[c][y][x] = -(Fp - Fm) / dx;
+          else
+            s_L[c][y][x] = (Fm - Fp) * inv_dx;
+        } else {
+          if constexpr (kExact)
+            s_L[c][y][x] = s_L[c][y][x] - (Fp - Fm) / dy;
+          else
+            s_L[c][y][x] = s_L[c][y][x] + (Fm - Fp) * inv_dy;
+        }
+      }
+    }
+    __syncthreads();
+  };
+  sweep(std::integral_constant<int, 0>{});
+  sweep(std::integral_constant<int, 1>{});
+
+  // ---- update of the owned cells -----------------------------------------------------------
+  R amx = R(0), amy = R(0);
+  int bad = 0;
+#pragma unroll
+  for (int k = 0; k < NOWN; ++k) {
+    const int o = tid + k * BS;
+    const int x = o % TX, y = o / TX;
+    if (o >= TX * TY || i0 + x >= nx || j0 + y >= ny) continue;
+    const long long at = (long long)(j0 + y) * nx + (i0 + x);
+    R unew[M];
+#pragma unroll
+    for (int c = 0; c < M; ++c) {
+      const R L = s_L[c][y][x];
+      const R us = s_u[c][y + 3][x + 3];
+      if (stage == 0)
+        unew[c] = L;
+      else if (stage == 1)
+        unew[c] = us + rdt * L;
+      else if (stage == 2)
+        unew[c] = R(0.75) * upt[k][c] + R(0.25) * (us + rdt * L);
+      else
+        unew[c] = R(1.0 / 3.0) * upt[k][c] + R(2.0 / 3.0) * (us + rdt * L);
+      dst[c * ncell + at] = unew[c];
+    }
+    if (stage != 0) {
+      int b0 = 0, b1 = 0;
+      R sx = spectral_radius<R, FLUX, M, 0>(unew, speed_x, gamma, b0);
+      R sy = spectral_radius<R, FLUX, M, 1>(unew, speed_y, gamma, b1);
+      if constexpr (FLUX == kAdvection) sy = fabs(speed_y);
+      amx = sx > amx ? sx : amx;
+      amy = sy > amy ? sy : amy;
+      bad = b0 > bad ? b0 : bad;
+    }
+  }
+  if (stage == 0) return;
+  amx = wave_max_nonneg(amx);
+  amy = wave_max_nonneg(amy);
+  const bool bad2 = __any(bad == 2), bad1 = __any(bad == 1);
+  if ((tid & 63) == 0) {
+    s_red[0][tid >> 6] = double_to_bits(double(amx));
+    s_red[1][tid >> 6] = double_to_bits(double(amy));
+    s_bad[tid >> 6] = bad2 ? 2 : (bad1 ? 1 : 0);
+  }
+  __syncthreads();
+  if (tid == 0) {
+    unsigned long long mx = 0ull, my = 0ull;
+    int w = 0;
+#pragma unroll
+    for (int k = 0; k < BS / 64; ++k) {
+      mx = s_red[0][k] > mx ? s_red[0][k] : mx;
+      my = s_red[1][k] > my ? s_red[1][k] : my;
+      w = s_bad[k] > w ? s_bad[k] : w;
+    }
+    const int slot = stage == 1 ? 1 : (stage == 2 ? 2 : 0);
+    if (w) {
+      const int code = w == 2 ? NPW_ENONPHYSICAL : NPW_ENONFINITE;
+      if (atomicCAS(&I->err, 0, code) == 0) {
+        I->err_stage = stage;
+        I->err_n = n;
+        I->err_t = t;
+        I->err_home = par;
+      }
+    } else {
+      const int k = (blockIdx.y * gridDim.x + blockIdx.x) % kSpread;
+      atomicMax(sp ? &sp[((slot * 2 + 0) * kSpread + k) * kSpreadStride] : &I->alpha[slot][0], mx);
+      atomicMax(sp ? &sp[((slot * 2 + 1) * kSpread + k) * kSpreadStride] : &I->alpha[slot][1], my);
+    }
+  }
+}
+
+}  // namespace npw

@@ -1,5 +1,6 @@
 // Kernel instantiations for the double bulk precision.
 #include "npw_kernels.h"
+#include "npw_kernels2d.h"
 
 namespace npw {
 
@@ -27,17 +28,33 @@ hipError_t launch_stage_f64(int flux, int ncomp, int block, const StageArgs& a, 
   }
 }
 
-hipError_t launch_init_f64(int flux, int ncomp, InstDev* inst, int ninst, void* P0, void* P1, hipStream_t s) {
+// 2D tiles of 64 x 8 cells (x contiguous), one workgroup each.
+constexpr int kTX = 64, kTY = 8;
+hipError_t launch_stage2d_f64(int flux, int ncomp, const StageArgs& a, hipStream_t s) {
+  const dim3 grid((unsigned)((a.nx + kTX - 1) / kTX), (unsigned)((a.ny + kTY - 1) / kTY)), block(256);
+  if (flux == kEuler && ncomp == 4)
+    stage2d_kernel<double, kEuler, 4, kTX, kTY><<<grid, block, 0, s>>>(a);
+  else if (flux == kAdvection && ncomp == 1)
+    stage2d_kernel<double, kAdvection, 1, kTX, kTY><<<grid, block, 0, s>>>(a);
+  else if (flux == kBurgers && ncomp == 1)
+    stage2d_kernel<double, kBurgers, 1, kTX, kTY><<<grid, block, 0, s>>>(a);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t launch_init_f64(int flux, int ncomp, InstDev* inst, int ninst, void* P0, void* P1,
+                           unsigned long long* spread, hipStream_t s) {
   if (ninst <= 0) return hipSuccess;
   const dim3 grid(ninst), block(256);
   if (flux == kAdvection && ncomp == 1)
-    init_kernel<double, kAdvection, 1><<<grid, block, 0, s>>>(inst, P0, P1);
+    init_kernel<double, kAdvection, 1><<<grid, block, 0, s>>>(inst, P0, P1, spread);
   else if (flux == kBurgers && ncomp == 1)
-    init_kernel<double, kBurgers, 1><<<grid, block, 0, s>>>(inst, P0, P1);
+    init_kernel<double, kBurgers, 1><<<grid, block, 0, s>>>(inst, P0, P1, spread);
   else if (flux == kEuler && ncomp == 3)
-    init_kernel<double, kEuler, 3><<<grid, block, 0, s>>>(inst, P0, P1);
+    init_kernel<double, kEuler, 3><<<grid, block, 0, s>>>(inst, P0, P1, spread);
   else if (flux == kEuler && ncomp == 4)
-    init_kernel<double, kEuler, 4><<<grid, block, 0, s>>>(inst, P0, P1);
+    init_kernel<double, kEuler, 4><<<grid, block, 0, s>>>(inst, P0, P1, spread);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();

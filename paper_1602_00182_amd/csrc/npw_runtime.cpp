@@ -38,8 +38,12 @@ struct npw_solver {
   void* P1 = nullptr;
   void* C = nullptr;
   void* scratch = nullptr;      // rhs destination when the caller passes host memory
-  std::map<int, hipGraphExec_t> graphs;  // steps per graph -> executable graph
+  unsigned long long* spread = nullptr;  // spread alpha slots (single-grid solvers)
+  std::map<int, hipGraphExec_t> graphs;  // (steps per graph, start parity) -> executable graph
   int sticky_err = 0;
+  bool batch = false;              // created by npweno_create_batch
+  std::vector<Tile> tiles_all;     // every tile of every instance
+  std::vector<char> settled;       // per instance: error already handled
 };
 
 namespace {
@@ -59,6 +63,7 @@ int validate(const npw_params* p) {
   if (p->abi_version != NPW_ABI_VERSION) return NPW_EINVAL;
   if (p->dim != 1 && p->dim != 2) return NPW_EINVAL;
   if (p->nx < 1 || (p->dim == 2 && p->ny < 1)) return NPW_EINVAL;
+  if (p->nx > (1 << 30) || (p->dim == 2 && p->ny > (1 << 30))) return NPW_EINVAL;
   if (p->flux == NPW_ADVECTION || p->flux == NPW_BURGERS) {
     if (p->ncomp != 1) return NPW_EINVAL;
   } else if (p->flux == NPW_EULER) {
@@ -76,7 +81,6 @@ int validate(const npw_params* p) {
   if (!finite_pos(p->cfl) || !finite_pos(p->eps_weno) || !finite_pos(p->eps_m)) return NPW_EINVAL;
   if (!(std::isfinite(p->dt_fixed) && p->dt_fixed >= 0.0)) return NPW_EINVAL;
   if (!std::isfinite(p->speed_x) || !std::isfinite(p->speed_y)) return NPW_EINVAL;
-  if (p->dim == 2) return NPW_EINVAL;  // the 2D stage kernel is not part of this build
   return NPW_OK;
 }
 
@@ -88,26 +92,35 @@ int env_block() {
 }
 
 hipError_t launch_stage(const npw_solver* s, const StageArgs& a, hipStream_t st) {
+  if (s->dim == 2)
+    return s->precision == NPW_FP64 ? npw::launch_stage2d_f64(s->flux, s->ncomp, a, st)
+                                    : npw::launch_stage2d_f32(s->flux, s->ncomp, a, st);
   return s->precision == NPW_FP64 ? npw::launch_stage_f64(s->flux, s->ncomp, s->block, a, st)
                                   : npw::launch_stage_f32(s->flux, s->ncomp, s->block, a, st);
 }
 
 hipError_t launch_init(const npw_solver* s, hipStream_t st) {
-  return s->precision == NPW_FP64 ? npw::launch_init_f64(s->flux, s->ncomp, s->d_inst, s->ninst, s->P0, s->P1, st)
-                                  : npw::launch_init_f32(s->flux, s->ncomp, s->d_inst, s->ninst, s->P0, s->P1, st);
+  return s->precision == NPW_FP64
+             ? npw::launch_init_f64(s->flux, s->ncomp, s->d_inst, s->ninst, s->P0, s->P1, s->spread, st)
+             : npw::launch_init_f32(s->flux, s->ncomp, s->d_inst, s->ninst, s->P0, s->P1, s->spread, st);
 }
 
-StageArgs stage_args(const npw_solver* s, int stage, void* out) {
+StageArgs stage_args(const npw_solver* s, int stage, int par, void* out) {
   StageArgs a;
   a.inst = s->d_inst;
-  a.tiles = s->d_tiles;
+  a.tiles = s->ninst == 1 ? nullptr : s->d_tiles;
   a.ntiles = s->ntiles;
   a.ntiles_dev = nullptr;
+  a.nx = s->h_inst[0].nx;
+  a.ny = s->h_inst[0].ny;
+  a.bc = s->h_inst[0].bc;
+  a.par = par;
   a.P0 = s->P0;
   a.P1 = s->P1;
   a.C = s->C;
   a.out = out;
   a.stage = stage;
+  a.spread = s->spread;
   return a;
 }
 
@@ -141,15 +154,18 @@ int push_static(npw_solver* s) {
   return NPW_OK;
 }
 
-hipGraphExec_t graph_for(npw_solver* s, int k) {
-  auto it = s->graphs.find(k);
+// Graph of k whole steps whose first step reads u^n from P[par]; the buffers alternate per step.
+hipGraphExec_t graph_for(npw_solver* s, int k, int par) {
+  const int key = 2 * k + par;
+  auto it = s->graphs.find(key);
   if (it != s->graphs.end()) return it->second;
   hipGraph_t g = nullptr;
   hipGraphExec_t ex = nullptr;
   if (hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal) != hipSuccess) return nullptr;
   bool ok = true;
   for (int i = 0; i < k && ok; ++i)
-    for (int st = 1; st <= 3 && ok; ++st) ok = launch_stage(s, stage_args(s, st, nullptr), s->stream) == hipSuccess;
+    for (int st = 1; st <= 3 && ok; ++st)
+      ok = launch_stage(s, stage_args(s, st, par ^ (i & 1), nullptr), s->stream) == hipSuccess;
   hipError_t e = hipStreamEndCapture(s->stream, &g);
   if (!ok || e != hipSuccess) {
     if (g) (void)hipGraphDestroy(g);
@@ -158,28 +174,70 @@ hipGraphExec_t graph_for(npw_solver* s, int k) {
   e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
   (void)hipGraphDestroy(g);
   if (e != hipSuccess) return nullptr;
-  s->graphs[k] = ex;
+  s->graphs[key] = ex;
   return ex;
 }
 
-// After a failed step: put the control word back at the last good step (its state is still in
-// P[n & 1]) and refresh alpha and the sums of that state.
-int settle_error(npw_solver* s) {
-  for (int b = 0; b < s->ninst; ++b) {
-    const InstDev& h = s->h_pin[b];
-    if (!h.err) continue;
-    Ctl c;
-    c.t = h.err_t;
-    c.dt = 0.0;
-    c.n = h.err_n;
-    c.active = 0;
-    c.pad = 0;
-    HIP_TRY(hipMemcpyAsync(reinterpret_cast<char*>(s->d_inst + b) + offsetof(InstDev, ctl), &c, sizeof(Ctl),
-                           hipMemcpyHostToDevice, s->stream));
-    if (s->sticky_err == 0) s->sticky_err = h.err;
-  }
+// After a failed step of instance b: put its control word back at the last good step (that
+// state is still in its home buffer) and refresh alpha and the sums of every state.
+int settle_error(npw_solver* s, int b) {
+  const InstDev& h = s->h_pin[b];
+  Ctl c;
+  c.t = h.err_t;
+  c.dt = 0.0;
+  c.n = h.err_n;
+  c.active = 0;
+  c.home = h.err_home;
+  HIP_TRY(hipMemcpyAsync(reinterpret_cast<char*>(s->d_inst + b) + offsetof(InstDev, ctl), &c, sizeof(Ctl),
+                         hipMemcpyHostToDevice, s->stream));
+  if (s->sticky_err == 0 && !s->batch) s->sticky_err = h.err;
   HIP_TRY(launch_init(s, s->stream));
   return pull(s);
+}
+
+void clear_graphs(npw_solver* s) {
+  for (auto& kv : s->graphs) (void)hipGraphExecDestroy(kv.second);
+  s->graphs.clear();
+}
+
+// Tile table of the instances flagged in `want`.  Tiles of finished instances cost one
+// early-exit workgroup each, so the table is only rebuilt when it is forced (start of a solve)
+// or when at most 3/4 of its tiles still belong to running instances.  Graphs hold the tile
+// count, so they are re-captured when it changes.
+int set_tiles(npw_solver* s, const std::vector<char>& want, bool force) {
+  std::vector<Tile> t;
+  t.reserve(s->tiles_all.size());
+  for (const Tile& x : s->tiles_all)
+    if (want[x.inst]) t.push_back(x);
+  if (!force && 4 * t.size() > 3 * (size_t)s->ntiles) return NPW_OK;
+  if (!t.empty())
+    HIP_TRY(hipMemcpyAsync(s->d_tiles, t.data(), sizeof(Tile) * t.size(), hipMemcpyHostToDevice, s->stream));
+  if ((int)t.size() != s->ntiles) clear_graphs(s);
+  s->ntiles = (int)t.size();
+  return NPW_OK;
+}
+
+// Stepped instances advance in lockstep, so their u^n must sit in the same ping-pong buffer:
+// move the minority to the majority's buffer (device copies) and report that buffer.
+int align_homes(npw_solver* s, int* gp_out) {
+  int votes[2] = {0, 0};
+  for (int b = 0; b < s->ninst; ++b)
+    if (!s->h_pin[b].err) votes[s->h_pin[b].ctl[0].home & 1]++;
+  const int gp = votes[1] > votes[0] ? 1 : 0;
+  bool moved = false;
+  for (int b = 0; b < s->ninst; ++b) {
+    const InstDev& h = s->h_pin[b];
+    if (h.err || h.ctl[0].home == gp) continue;
+    const size_t len = (size_t)s->ncomp * (size_t)(h.nx * h.ny) * s->esize;
+    char* from = static_cast<char*>(h.ctl[0].home ? s->P1 : s->P0) + (size_t)h.off * s->esize;
+    char* to = static_cast<char*>(gp ? s->P1 : s->P0) + (size_t)h.off * s->esize;
+    HIP_TRY(hipMemcpyAsync(to, from, len, hipMemcpyDeviceToDevice, s->stream));
+    HIP_TRY(hipMemcpyAsync(reinterpret_cast<char*>(s->d_inst + b) + offsetof(InstDev, ctl) + offsetof(Ctl, home),
+                           &gp, sizeof(int), hipMemcpyHostToDevice, s->stream));
+    moved = true;
+  }
+  *gp_out = gp;
+  return moved ? pull(s) : NPW_OK;
 }
 
 void fill_stats(const npw_solver* s, int b, npw_stats* st) {
@@ -203,6 +261,7 @@ void release(npw_solver* s) {
   if (s->P1) (void)hipFree(s->P1);
   if (s->C) (void)hipFree(s->C);
   if (s->scratch) (void)hipFree(s->scratch);
+  if (s->spread) (void)hipFree(s->spread);
   if (s->d_inst) (void)hipFree(s->d_inst);
   if (s->d_tiles) (void)hipFree(s->d_tiles);
   if (s->h_pin) (void)hipHostFree(s->h_pin);
@@ -219,6 +278,8 @@ InstDev make_inst(const npw_params* p, long long off) {
   d.ny = p->dim == 2 ? p->ny : 1;
   d.dx = (p->x1 - p->x0) / (double)p->nx;
   d.dy = p->dim == 2 ? (p->y1 - p->y0) / (double)p->ny : 1.0;
+  d.inv_dx = 1.0 / d.dx;
+  d.inv_dy = 1.0 / d.dy;
   d.cfl = p->cfl;
   d.dt_fixed = p->dt_fixed;
   d.T = 0.0;
@@ -235,9 +296,9 @@ InstDev make_inst(const npw_params* p, long long off) {
   return d;
 }
 
-int upload_state(npw_solver* s, const void* u, int on_device, double t) {
-  const size_t bytes = s->total * s->esize;
-  HIP_TRY(hipMemcpyAsync(s->P0, u, bytes, on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s->stream));
+// Every instance restarts at time t from the state in P0 (step count, error and home reset),
+// followed by the state check.  Returns the first error the check finds.
+int reset_instances(npw_solver* s, double t) {
   for (int b = 0; b < s->ninst; ++b) {
     InstDev& h = s->h_inst[b];
     std::memset(h.ctl, 0, sizeof h.ctl);
@@ -247,16 +308,21 @@ int upload_state(npw_solver* s, const void* u, int on_device, double t) {
     h.err_stage = 0;
     h.err_n = 0;
     h.err_t = 0.0;
+    h.err_home = 0;
   }
   HIP_TRY(hipMemcpyAsync(s->d_inst, s->h_inst.data(), sizeof(InstDev) * s->ninst, hipMemcpyHostToDevice, s->stream));
   HIP_TRY(launch_init(s, s->stream));
   int rc = pull(s);
   if (rc) return rc;
   s->sticky_err = 0;
-  return s->h_pin[0].err;
+  for (int b = 0; b < s->ninst; ++b)
+    if (s->h_pin[b].err) return s->h_pin[b].err;
+  return NPW_OK;
 }
 
 }  // namespace
+
+static int run_steps(npw_solver* s, const double* T, int64_t max_steps, int64_t* taken);
 
 extern "C" {
 
@@ -302,35 +368,50 @@ void npweno_default_params(npw_params* p) {
   p->dt_fixed = 0.0;
 }
 
-int npweno_create(const npw_params* p, const void* u0, int u0_on_device, void* hip_stream, npw_solver** out) {
+// Build a solver for `count` instances sharing precision, flux and dimension.  u0[b] holds the
+// initial state of instance b.
+static int create_common(const npw_params* p, int32_t count, const void* const* u0, int on_device, void* hip_stream,
+                         bool batch, npw_solver** out) {
   if (!out) return NPW_EINVAL;
   *out = nullptr;
-  int rc = validate(p);
-  if (rc) return rc;
-  if (!u0) return NPW_EINVAL;
+  if (!p || !u0 || count < 1) return NPW_EINVAL;
+  for (int b = 0; b < count; ++b) {
+    int rc = validate(&p[b]);
+    if (rc) return rc;
+    if (batch && p[b].dim != 1) return NPW_EINVAL;  // batches are 1D
+    if (!u0[b]) return NPW_EINVAL;
+    if (p[b].precision != p[0].precision || p[b].flux != p[0].flux || p[b].ncomp != p[0].ncomp ||
+        p[b].dim != p[0].dim)
+      return NPW_EINVAL;
+  }
   npw_solver* s = new (std::nothrow) npw_solver();
   if (!s) return NPW_ENOMEM;
-  s->precision = p->precision;
-  s->flux = p->flux;
-  s->ncomp = p->ncomp;
-  s->dim = p->dim;
-  s->esize = p->precision == NPW_FP64 ? sizeof(double) : sizeof(float);
-  s->ninst = 1;
+  s->precision = p[0].precision;
+  s->flux = p[0].flux;
+  s->ncomp = p[0].ncomp;
+  s->dim = p[0].dim;
+  s->esize = p[0].precision == NPW_FP64 ? sizeof(double) : sizeof(float);
+  s->ninst = count;
+  s->batch = batch;
   s->block = env_block();
   s->user = reinterpret_cast<hipStream_t>(hip_stream);
-  const long long ncell = p->nx * (p->dim == 2 ? p->ny : 1);
-  s->total = (size_t)ncell * (size_t)p->ncomp;
-  s->h_inst.push_back(make_inst(p, 0));
   const int tile = s->block - 2;
-  std::vector<Tile> tiles;
-  for (long long st = 0; st < p->nx; st += tile) {
-    Tile t;
-    t.inst = 0;
-    t.pad = 0;
-    t.start = st;
-    tiles.push_back(t);
+  long long off = 0;
+  for (int b = 0; b < count; ++b) {
+    s->h_inst.push_back(make_inst(&p[b], off));
+    for (long long st = 0; st < p[b].nx; st += tile) {
+      Tile t;
+      t.inst = b;
+      t.bc = p[b].bc;
+      t.start = st;
+      t.nx = p[b].nx;
+      t.off = off;
+      s->tiles_all.push_back(t);
+    }
+    off += (long long)p[b].ncomp * p[b].nx * (p[b].dim == 2 ? p[b].ny : 1);
   }
-  s->ntiles = (int)tiles.size();
+  s->total = (size_t)off;
+  s->ntiles = (int)s->tiles_all.size();
   const size_t bytes = s->total * s->esize;
   // Graph capture needs a real stream: the legacy default stream gets a private stream that is
   // ordered against it with an event at every entry point.
@@ -348,18 +429,27 @@ int npweno_create(const npw_params* p, const void* u0, int u0_on_device, void* h
     return NPW_EHIP;
   }
   if (hipMalloc(&s->P0, bytes) != hipSuccess || hipMalloc(&s->P1, bytes) != hipSuccess ||
-      hipMalloc(&s->C, bytes) != hipSuccess || hipMalloc(&s->d_inst, sizeof(InstDev)) != hipSuccess ||
-      hipMalloc(&s->d_tiles, sizeof(Tile) * tiles.size()) != hipSuccess ||
-      hipHostMalloc(&s->h_pin, sizeof(InstDev), hipHostMallocDefault) != hipSuccess) {
+      hipMalloc(&s->C, bytes) != hipSuccess || hipMalloc(&s->d_inst, sizeof(InstDev) * count) != hipSuccess ||
+      hipMalloc(&s->d_tiles, sizeof(Tile) * s->tiles_all.size()) != hipSuccess ||
+      hipHostMalloc(&s->h_pin, sizeof(InstDev) * count, hipHostMallocDefault) != hipSuccess ||
+      (!batch && hipMalloc(&s->spread, sizeof(unsigned long long) * npw::kSpreadWords) != hipSuccess)) {
     release(s);
     return NPW_ENOMEM;
   }
-  if (enter(s) || hipMemcpyAsync(s->d_tiles, tiles.data(), sizeof(Tile) * tiles.size(), hipMemcpyHostToDevice,
-                                 s->stream) != hipSuccess) {
+  if (enter(s) || hipMemcpyAsync(s->d_tiles, s->tiles_all.data(), sizeof(Tile) * s->tiles_all.size(),
+                                 hipMemcpyHostToDevice, s->stream) != hipSuccess) {
     release(s);
     return NPW_EHIP;
   }
-  rc = upload_state(s, u0, u0_on_device, 0.0);
+  int rc = NPW_OK;
+  for (int b = 0; b < count && rc == NPW_OK; ++b) {
+    const size_t len = (size_t)p[b].ncomp * (size_t)(p[b].nx * (p[b].dim == 2 ? p[b].ny : 1)) * s->esize;
+    char* dst = static_cast<char*>(s->P0) + (size_t)s->h_inst[b].off * s->esize;
+    if (hipMemcpyAsync(dst, u0[b], len, on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s->stream) !=
+        hipSuccess)
+      rc = NPW_EHIP;
+  }
+  if (rc == NPW_OK) rc = reset_instances(s, 0.0);
   if (rc == NPW_OK) rc = leave(s);
   if (rc) {
     release(s);
@@ -369,57 +459,137 @@ int npweno_create(const npw_params* p, const void* u0, int u0_on_device, void* h
   return NPW_OK;
 }
 
-int npweno_write(npw_solver* s, const void* u, int on_device, double t) {
-  if (!s || !u || !std::isfinite(t)) return NPW_EINVAL;
+int npweno_create(const npw_params* p, const void* u0, int u0_on_device, void* hip_stream, npw_solver** out) {
+  const void* one[1] = {u0};
+  return create_common(p, 1, one, u0_on_device, hip_stream, false, out);
+}
+
+int npweno_create_batch(const npw_params* params, int32_t count, const void* const* u0, int on_device,
+                        void* hip_stream, npw_solver** out) {
+  return create_common(params, count, u0, on_device, hip_stream, true, out);
+}
+
+int npweno_solve_batch(npw_solver* s, const double* t_final, int64_t max_steps, npw_stats* per_instance) {
+  if (!s || !t_final) return NPW_EINVAL;
   int rc = enter(s);
   if (rc) return rc;
-  rc = upload_state(s, u, on_device, t);
+  rc = run_steps(s, t_final, max_steps, nullptr);
+  if (per_instance) {
+    HIP_TRY(launch_init(s, s->stream));
+    if (pull(s) == NPW_OK)
+      for (int b = 0; b < s->ninst; ++b) fill_stats(s, b, &per_instance[b]);
+  }
   int rc2 = leave(s);
   return rc ? rc : rc2;
 }
 
-static int run_steps(npw_solver* s, double t_final, int64_t max_steps, int64_t* taken) {
+int npweno_read_instance(const npw_solver* cs, int32_t index, void* u_out, int out_on_device) {
+  if (!cs || !u_out || index < 0 || index >= cs->ninst) return NPW_EINVAL;
+  npw_solver* s = const_cast<npw_solver*>(cs);
+  int rc = enter(s);
+  if (rc) return rc;
+  rc = pull(s);
+  if (rc) return rc;
+  const InstDev& h = s->h_pin[index];
+  const size_t len = (size_t)s->ncomp * (size_t)(h.nx * h.ny) * s->esize;
+  const char* src = static_cast<const char*>(h.ctl[0].home ? s->P1 : s->P0) + (size_t)h.off * s->esize;
+  HIP_TRY(hipMemcpyAsync(u_out, src, len, out_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, s->stream));
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  return leave(s);
+}
+
+int npweno_get_stats_instance(const npw_solver* cs, int32_t index, npw_stats* stats) {
+  if (!cs || !stats || index < 0 || index >= cs->ninst) return NPW_EINVAL;
+  npw_solver* s = const_cast<npw_solver*>(cs);
+  int rc = enter(s);
+  if (rc) return rc;
+  HIP_TRY(launch_init(s, s->stream));
+  rc = pull(s);
+  if (rc) return rc;
+  fill_stats(s, index, stats);
+  return leave(s);
+}
+
+int npweno_instance_count(const npw_solver* s) { return s ? s->ninst : 0; }
+
+int npweno_write(npw_solver* s, const void* u, int on_device, double t) {
+  if (!s || !u || !std::isfinite(t)) return NPW_EINVAL;
+  int rc = enter(s);
+  if (rc) return rc;
+  HIP_TRY(hipMemcpyAsync(s->P0, u, s->total * s->esize, on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
+                         s->stream));
+  rc = reset_instances(s, t);
+  int rc2 = leave(s);
+  return rc ? rc : rc2;
+}
+
+// Advance every instance towards its target T[b] (same stopping rule as a single solve) or until
+// max_steps graph steps were launched.  Instances that fail are restored to their last good
+// step and left behind; the others continue.  Returns the first error seen (NPW_OK if none).
+static int run_steps(npw_solver* s, const double* T, int64_t max_steps, int64_t* taken) {
   if (taken) *taken = 0;
-  if (!std::isfinite(t_final)) return NPW_EINVAL;
+  for (int b = 0; b < s->ninst; ++b)
+    if (!std::isfinite(T[b])) return NPW_EINVAL;
   if (s->sticky_err) return s->sticky_err;
-  for (auto& h : s->h_inst) {
-    h.T = t_final;
-    h.tol = 1e-12 * std::max(1.0, std::fabs(t_final));
+  for (int b = 0; b < s->ninst; ++b) {
+    s->h_inst[b].T = T[b];
+    s->h_inst[b].tol = 1e-12 * std::max(1.0, std::fabs(T[b]));
   }
   int rc = push_static(s);
   if (rc) return rc;
-  int64_t done_steps = 0;
-  int k = 1;  // steps per graph replay; grows while the solve is far from its end
   rc = pull(s);
   if (rc) return rc;
-  const long long n_start = s->h_pin[0].ctl[0].n;
+  s->settled.assign(s->ninst, 0);
+  int gp = 0;
+  rc = align_homes(s, &gp);
+  if (rc) return rc;
+  const long long n0 = s->h_pin[0].ctl[0].n;
+  int64_t launched = 0;
+  int first_err = 0;
+  std::vector<char> active(s->ninst, 0);
   while (true) {
-    bool all_done = true;
+    int nactive = 0;
+    double est = 0.0;
+    int home = gp;
     for (int b = 0; b < s->ninst; ++b) {
       const InstDev& h = s->h_pin[b];
-      if (h.err) return settle_error(s) ? NPW_EHIP : h.err;
-      if (t_final - h.ctl[0].t > s->h_inst[b].tol) all_done = false;
+      active[b] = 0;
+      if (h.err) {
+        if (!s->settled[b]) {
+          s->settled[b] = 1;
+          if (!first_err) first_err = h.err;
+          if (settle_error(s, b)) return NPW_EHIP;
+        }
+        continue;
+      }
+      const double rem = s->h_inst[b].T - h.ctl[0].t;
+      if (rem > s->h_inst[b].tol) {
+        active[b] = 1;
+        ++nactive;
+        home = h.ctl[0].home;
+        const double dt = h.ctl[1].dt;
+        est = std::max(est, dt > 0.0 ? rem / dt : (double)kMaxGraphSteps);
+      }
     }
-    done_steps = s->h_pin[0].ctl[0].n - n_start;
-    if (taken) *taken = done_steps;
-    if (all_done || (max_steps >= 0 && done_steps >= max_steps)) break;
-    // choose the graph size: estimate the remaining steps from the last dt
-    int want = kMaxGraphSteps;
-    const InstDev& h0 = s->h_pin[0];
-    if (s->ninst == 1 && h0.ctl[1].dt > 0.0) {
-      const double est = (t_final - h0.ctl[0].t) / h0.ctl[1].dt;
-      want = est < 1.0 ? 1 : (int)std::min((double)kMaxGraphSteps, std::ceil(est));
+    if (taken) *taken = s->ninst == 1 ? (int64_t)(s->h_pin[0].ctl[0].n - n0) : launched;
+    const int64_t progress = s->ninst == 1 ? (int64_t)(s->h_pin[0].ctl[0].n - n0) : launched;
+    if (nactive == 0 || (max_steps >= 0 && progress >= max_steps)) break;
+    if (s->batch) {
+      rc = set_tiles(s, active, launched == 0);
+      if (rc) return rc;
     }
-    if (max_steps >= 0) want = (int)std::min<int64_t>(want, max_steps - done_steps);
-    k = 1;
+    int want = est < 1.0 ? 1 : (int)std::min((double)kMaxGraphSteps, std::ceil(est));
+    if (max_steps >= 0) want = (int)std::min<int64_t>(want, max_steps - progress);
+    int k = 1;
     while (k * 4 <= want) k *= 4;
-    hipGraphExec_t g = graph_for(s, k);
+    hipGraphExec_t g = graph_for(s, k, home);
     if (!g) return NPW_EHIP;
     HIP_TRY(hipGraphLaunch(g, s->stream));
+    launched += k;
     rc = pull(s);
     if (rc) return rc;
   }
-  return NPW_OK;
+  return first_err;
 }
 
 int npweno_step(npw_solver* s, double t_final, double* dt_taken) {
@@ -427,7 +597,8 @@ int npweno_step(npw_solver* s, double t_final, double* dt_taken) {
   int rc = enter(s);
   if (rc) return rc;
   int64_t taken = 0;
-  rc = run_steps(s, t_final, 1, &taken);
+  std::vector<double> T(s->ninst, t_final);
+  rc = run_steps(s, T.data(), 1, &taken);
   if (dt_taken) *dt_taken = (rc == NPW_OK && taken == 1) ? s->h_pin[0].ctl[1].dt : 0.0;
   int rc2 = leave(s);
   return rc ? rc : rc2;
@@ -437,7 +608,8 @@ int npweno_solve(npw_solver* s, double t_final, int64_t max_steps, npw_stats* st
   if (!s) return NPW_EINVAL;
   int rc = enter(s);
   if (rc) return rc;
-  rc = run_steps(s, t_final, max_steps, nullptr);
+  std::vector<double> T(s->ninst, t_final);
+  rc = run_steps(s, T.data(), max_steps, nullptr);
   if (stats) {
     HIP_TRY(launch_init(s, s->stream));
     if (pull(s) == NPW_OK) fill_stats(s, 0, stats);
@@ -457,7 +629,17 @@ int npweno_rhs(npw_solver* s, void* L_out, int out_on_device) {
     if (!s->scratch && hipMalloc(&s->scratch, bytes) != hipSuccess) return NPW_ENOMEM;
     dst = s->scratch;
   }
-  HIP_TRY(launch_stage(s, stage_args(s, 0, dst), s->stream));
+  rc = pull(s);
+  if (rc) return rc;
+  int gp = 0;
+  rc = align_homes(s, &gp);
+  if (rc) return rc;
+  if (s->batch) {  // every tile, including those of finished instances
+    std::vector<char> all(s->ninst, 1);
+    rc = set_tiles(s, all, true);
+    if (rc) return rc;
+  }
+  HIP_TRY(launch_stage(s, stage_args(s, 0, gp, dst), s->stream));
   if (!out_on_device) HIP_TRY(hipMemcpyAsync(L_out, dst, bytes, hipMemcpyDeviceToHost, s->stream));
   HIP_TRY(hipStreamSynchronize(s->stream));
   return leave(s);
@@ -470,10 +652,14 @@ int npweno_read(const npw_solver* cs, void* u_out, int out_on_device) {
   if (rc) return rc;
   rc = pull(s);
   if (rc) return rc;
-  const long long n = s->h_pin[0].ctl[0].n;
-  const void* src = (n & 1) ? s->P1 : s->P0;
-  HIP_TRY(hipMemcpyAsync(u_out, src, s->total * s->esize, out_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
-                         s->stream));
+  const hipMemcpyKind kind = out_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+  for (int b = 0; b < s->ninst; ++b) {  // each instance from the buffer that holds its u^n
+    const InstDev& h = s->h_pin[b];
+    const size_t at = (size_t)h.off * s->esize;
+    const size_t len = (size_t)s->ncomp * (size_t)(h.nx * h.ny) * s->esize;
+    const char* src = static_cast<const char*>(h.ctl[0].home ? s->P1 : s->P0) + at;
+    HIP_TRY(hipMemcpyAsync(static_cast<char*>(u_out) + at, src, len, kind, s->stream));
+  }
   HIP_TRY(hipStreamSynchronize(s->stream));
   return leave(s);
 }

@@ -1,0 +1,98 @@
+"""GPU parity of the 2D dimension-by-dimension path (Section 7, eq. 2DIntegral, one midpoint
+point per face) against the FP64 oracle."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1602_00182_amd import binding as B
+from paper_1602_00182_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(f"[case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+def _oracle_problem(w):
+    return O.Problem(nx=w.nx, flux=w.flux, dim=w.dim, ny=w.ny, ncomp=w.ncomp, bc=w.bc, x0=w.x0, x1=w.x1,
+                     y0=w.y0, y1=w.y1, speed_x=w.speed_x, speed_y=w.speed_y, gamma=w.gamma, cfl=w.cfl,
+                     eps_weno=w.eps_weno, eps_m=w.eps_m, recon=w.recon, switch_mode=w.switch_mode,
+                     dt_fixed=w.dt_fixed)
+
+
+def _quadrants(n, ny, seed=5):
+    w = I.euler2d_quadrants(n=max(n, ny), seed=seed)
+    if n == ny:
+        return w
+    U = w.u0.reshape(4, w.ny, w.nx)[:, :ny, :n].copy()
+    return w.with_(nx=n, ny=ny, u0=U.reshape(-1))
+
+
+@pytest.mark.parametrize("n,ny,bc", [(96, 80, I.TRANSMISSIVE), (70, 13, I.PERIODIC), (5, 3, I.PERIODIC)])
+def test_euler2d_fp64_steps(n, ny, bc):
+    _say(f"euler2d fp64 {n}x{ny} bc={bc}")
+    w = _quadrants(max(n, ny), max(n, ny))
+    U = w.u0.reshape(4, w.ny, w.nx)[:, :ny, :n].copy().reshape(-1)
+    w = w.with_(nx=n, ny=ny, u0=U, bc=bc)
+    with B.Solver(w.u0, **B.workload_params(w)) as s:
+        L = s.rhs()
+        st = s.solve(w.T, max_steps=12)
+        u = s.read()
+    Lo, _ = O.rhs(_oracle_problem(w), w.u0)
+    assert np.array_equal(L, Lo)
+    uo, to, no = O.solve(_oracle_problem(w), w.u0, w.T, max_steps=12)
+    assert st["nsteps"] == no and st["t"] == to
+    assert np.array_equal(u, uo)
+
+
+@pytest.mark.parametrize("flux", [I.ADVECTION, I.BURGERS])
+def test_scalar2d_fp64(flux):
+    _say(f"scalar2d fp64 flux={flux}")
+    n, ny = 72, 40
+    xc = (np.arange(n) + 0.5) / n
+    yc = (np.arange(ny) + 0.5) / ny
+    X, Y = np.meshgrid(xc, yc)
+    rng = np.random.default_rng(2)
+    u0 = 0.3 + np.sin(2 * np.pi * (X + Y)) + 0.05 * rng.random((ny, n))
+    w = I.Workload(name="s2", nx=n, ny=ny, dim=2, flux=flux, u0=u0.reshape(-1), T=0.2, x0=0, x1=1, y0=0, y1=1,
+                   speed_x=1.0, speed_y=-0.5, cfl=0.4)
+    with B.Solver(w.u0, **B.workload_params(w)) as s:
+        st = s.solve(w.T)
+        u = s.read()
+    uo, to, no = O.solve(_oracle_problem(w), w.u0, w.T)
+    assert st["nsteps"] == no
+    assert np.array_equal(u, uo)
+
+
+def test_euler2d_fp32():
+    _say("euler2d fp32")
+    w = _quadrants(128, 128)
+    u32 = np.asarray(w.u0, np.float32)
+    with B.Solver(u32, **B.workload_params(w, B.FP32)) as s:
+        s.solve(w.T, max_steps=30)
+        u = s.read().astype(np.float64)
+    uo, _, _ = O.solve(_oracle_problem(w), u32.astype(np.float64), w.T, max_steps=30)
+    assert np.mean(np.abs(u - uo)) <= 1e-5
+    assert np.max(np.abs(u - uo)) <= 1e-3  # near the quadrant discontinuities
+
+
+def test_euler2d_full_size_one_step():
+    """The 2048 x 2048 four-quadrant workload in the benchmark's launch configuration: one
+    whole RK step, every cell compared (double bulk, bit for bit; float bulk within 1e-5)."""
+    _say("euler2d 2048^2 one step")
+    w = I.euler2d_quadrants()
+    with B.Solver(w.u0, **B.workload_params(w)) as s:
+        s.solve(w.T, max_steps=1)
+        u = s.read()
+    u32 = np.asarray(w.u0, np.float32)
+    with B.Solver(u32, **B.workload_params(w, B.FP32)) as s:
+        s.solve(w.T, max_steps=1)
+        v = s.read().astype(np.float64)
+    uo, _, _ = O.solve(_oracle_problem(w), w.u0, w.T, max_steps=1)
+    assert np.array_equal(u, uo)
+    vo, _, _ = O.solve(_oracle_problem(w), u32.astype(np.float64), w.T, max_steps=1)
+    assert np.max(np.abs(v - vo)) <= 1e-5

@@ -1,0 +1,99 @@
+"""GPU batches (one stage launch for many ragged instances): every instance must give exactly
+what it gives when solved alone, and agree with the FP64 oracle."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1602_00182_amd import binding as B
+from paper_1602_00182_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(f"[case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+def _oracle_problem(w):
+    return O.Problem(nx=w.nx, flux=w.flux, dim=w.dim, ny=w.ny, ncomp=w.ncomp, bc=w.bc, x0=w.x0, x1=w.x1,
+                     y0=w.y0, y1=w.y1, speed_x=w.speed_x, speed_y=w.speed_y, gamma=w.gamma, cfl=w.cfl,
+                     eps_weno=w.eps_weno, eps_m=w.eps_m, recon=w.recon, switch_mode=w.switch_mode,
+                     dt_fixed=w.dt_fixed)
+
+
+def _states(ws, prec):
+    dt = np.float64 if prec == B.FP64 else np.float32
+    return [np.asarray(w.u0, dt) for w in ws]
+
+
+@pytest.mark.parametrize("prec", [B.FP64, B.FP32])
+def test_euler_batch_matches_single_and_oracle(prec):
+    _say(f"euler batch prec={prec}")
+    ws = I.euler_riemann_batch(count=10, seed=3, nmin=256, nmax=900)
+    ws[3] = ws[3].with_(bc=I.PERIODIC)  # per-instance parameters may differ
+    ws[5] = ws[5].with_(cfl=0.3)
+    T = [0.2 - 0.01 * b for b in range(len(ws))]
+    states = _states(ws, prec)
+    with B.Batch(states, [B.workload_params(w, prec) for w in ws]) as bt:
+        stats, rc = bt.solve(T)
+        got = [bt.read(b) for b in range(len(ws))]
+    assert rc == B.OK
+    for b, w in enumerate(ws):
+        with B.Solver(states[b], **B.workload_params(w, prec)) as s:
+            st = s.solve(T[b])
+            alone = s.read()
+        assert st["nsteps"] == stats[b]["nsteps"] and st["t"] == stats[b]["t"]
+        assert np.array_equal(alone, got[b]), b
+        if prec == B.FP64:
+            uo, to, no = O.solve(_oracle_problem(w), w.u0, T[b])
+            assert no == stats[b]["nsteps"]
+            assert np.max(np.abs(got[b] - uo)) <= 1e-12
+
+
+def test_scalar_batch_with_ragged_sizes_fp64():
+    _say("scalar batch ragged")
+    rng = np.random.default_rng(4)
+    ws = []
+    for b, n in enumerate([1, 7, 253, 254, 255, 509, 1000]):
+        u0 = 0.5 + I.sine_cell_averages(n) + 0.1 * rng.uniform(-1, 1, n)
+        ws.append(I.Workload(name=f"s{b}", nx=n, flux=I.BURGERS, u0=u0, T=0.3,
+                             bc=I.PERIODIC if b % 2 else I.TRANSMISSIVE))
+    with B.Batch(_states(ws, B.FP64), [B.workload_params(w) for w in ws]) as bt:
+        stats, rc = bt.solve(0.3)
+        for b, w in enumerate(ws):
+            uo, _, no = O.solve(_oracle_problem(w), w.u0, 0.3)
+            assert stats[b]["nsteps"] == no
+            assert np.array_equal(bt.read(b), uo), b
+
+
+def test_batch_error_is_isolated():
+    _say("batch error isolation")
+    ws = I.euler_riemann_batch(count=4, seed=9, nmin=300, nmax=400)
+    bad = I.burgers_noisy(n=300, seed=1, cfl=40.0, T=1000.0)
+    ws2 = [I.burgers_noisy(n=300 + 10 * b, seed=b) for b in range(3)] + [bad]
+    with B.Batch(_states(ws2, B.FP64), [B.workload_params(w) for w in ws2]) as bt:
+        stats, rc = bt.solve([w.T for w in ws2], raise_on_error=False)
+        assert rc == B.ENONFINITE
+        assert stats[3]["err"] == B.ENONFINITE
+        for b in range(3):
+            assert stats[b]["err"] == 0
+            uo, to, _ = O.solve(_oracle_problem(ws2[b]), ws2[b].u0, ws2[b].T)
+            assert np.array_equal(bt.read(b), uo)
+        u_bad = bt.read(3)
+        assert np.all(np.isfinite(u_bad))
+    del ws
+
+
+def test_batch_second_solve_continues():
+    _say("batch resume")
+    ws = [I.burgers_noisy(n=400 + 37 * b, seed=b) for b in range(5)]
+    with B.Batch(_states(ws, B.FP64), [B.workload_params(w) for w in ws]) as bt:
+        bt.solve([0.05 * (b + 1) for b in range(5)])  # instances stop at different steps
+        bt.solve(0.3)
+        for b, w in enumerate(ws):
+            uo, t1, _ = O.solve(_oracle_problem(w), w.u0, 0.05 * (b + 1))
+            uo, _, _ = O.solve(_oracle_problem(w), uo, 0.3, t=t1)
+            assert np.array_equal(bt.read(b), uo), b

@@ -180,8 +180,12 @@ def test_rhs_fp32_one_stage():
     u32 = np.asarray(u0, np.float32)
     with _solver(w, B.FP32, u0=u32) as s:
         L = s.rhs().astype(np.float64)
-    Lo, _ = O.rhs(_oracle_problem(w), u32.astype(np.float64))
-    assert np.max(np.abs(L - Lo)) <= 1e-4 * np.abs(Lo).max()
+    Lo, (alpha, _) = O.rhs(_oracle_problem(w), u32.astype(np.float64))
+    # L = -(F+ - F-)/dx: float rounding of the interface fluxes (|F| <= u^2/2 + alpha |u|) is
+    # amplified by 1/dx; allow 32 float ulps of the flux scale per interface.
+    umax = float(np.abs(u32).max())
+    tol = 32 * np.finfo(np.float32).eps * (0.5 * umax * umax + alpha * umax) / w.dx
+    assert np.max(np.abs(L - Lo)) <= tol
 
 
 def test_sod_fp32():
@@ -320,4 +324,7 @@ def test_full_size_burgers_full_solve_conserves_fp64():
         st = s.solve(w.T)
     assert st["t"] == pytest.approx(w.T, abs=1e-12)
     assert 40000 < st["nsteps"] < 60000
-    assert abs(st["mass"][0] - m0) <= 1e-13 * np.abs(w.u0).sum() * w.dx
+    # the last RK stage weighs u^n and u^(2) with fl(1/3) + fl(2/3) = 1 - 2^-54 (exactly), so any
+    # double evaluation of the scheme, the oracle's included, loses about 2^-54 of the cell-average
+    # sum per step (46977 steps: 2.6e-12, as observed)
+    assert abs(st["mass"][0] - m0) <= 4 * st["nsteps"] * 2.0 ** -53 * abs(m0)
