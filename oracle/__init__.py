@@ -24,7 +24,7 @@ _LIB = os.path.join(_HERE, "libnpw_oracle.so")
 
 ADVECTION, BURGERS, EULER = 0, 1, 2
 PERIODIC, TRANSMISSIVE = 0, 1
-RBF_WENO5, WENO5_JS = 0, 1
+RBF_WENO5, WENO5_JS, RBF_ENO3, ENO3 = 0, 1, 2, 3
 SWITCH_MONOTONE, SWITCH_OFF = 0, 1
 OK, EINVAL, ENONFINITE, ENONPHYSICAL = 0, -1, -4, -5
 
@@ -110,6 +110,12 @@ def lib():
         L.npo_recon_minus.restype = ctypes.c_double
         L.npo_recon_plus.argtypes = [_D, ctypes.c_double, ctypes.c_double]
         L.npo_recon_plus.restype = ctypes.c_double
+        L.npo_eno_stencil.argtypes = [_D]
+        L.npo_eno_stencil.restype = ctypes.c_int
+        L.npo_eno_minus.argtypes = [_D, ctypes.c_double]
+        L.npo_eno_minus.restype = ctypes.c_double
+        L.npo_eno_plus.argtypes = [_D, ctypes.c_double]
+        L.npo_eno_plus.restype = ctypes.c_double
         L.npo_line_states.argtypes = [P, _D, ctypes.c_long, _D, _D, _D, _I]
         L.npo_alpha.argtypes = [P, _D, _D]
         L.npo_alpha.restype = ctypes.c_int
@@ -165,6 +171,19 @@ def recon_minus(u5, eta_right, eps=1e-6) -> float:
 def recon_plus(u5, eta_left, eps=1e-6) -> float:
     u5 = _f64(u5)
     return lib().npo_recon_plus(_dp(u5), eta_left, eps)
+
+
+def eno_stencil(u5) -> int:
+    u5 = _f64(u5)
+    return lib().npo_eno_stencil(_dp(u5))
+
+
+def eno_minus(u5, eta_right) -> float:
+    return lib().npo_eno_minus(_dp(_f64(u5)), eta_right)
+
+
+def eno_plus(u5, eta_left) -> float:
+    return lib().npo_eno_plus(_dp(_f64(u5)), eta_left)
 
 
 def line_states(pb: Problem, line):

@@ -161,6 +161,39 @@ double npo_recon_plus(const double u5[5], double eta_left, double eps) {
 }
 
 /* ------------------------------------------------------------------------------------ */
+/* ENO stencil of cell i (Section 2; Newton divided differences as in Shu's notes): start   */
+/* from {i}, then twice add the neighbour (left or right) whose next divided difference of  */
+/* the primitive is smaller in magnitude.  With uniform cells those divided differences are */
+/* proportional to undivided differences of the averages.  Reading: on a tie the right-hand */
+/* cell is taken (strict "<" for the left).  u5 = (u_{i-2}..u_{i+2}); returns r such that    */
+/* the stencil is S_r(i) = {i-r, .., i-r+2}.                                                */
+/* ------------------------------------------------------------------------------------ */
+int npo_eno_stencil(const double u5[5]) {
+  /* level 2: {i-1, i} or {i, i+1} */
+  int left = 0; /* cells added on the left so far */
+  double dl = fabs(u5[2] - u5[1]), dr = fabs(u5[3] - u5[2]);
+  if (dl < dr) left = 1;
+  /* level 3: current stencil {i-left, i-left+1}; candidates extend it by one cell */
+  int l = 2 - left; /* index in u5 of the stencil's first cell */
+  double sl = fabs(u5[l + 1] - 2.0 * u5[l] + u5[l - 1]);
+  double sr = fabs(u5[l + 2] - 2.0 * u5[l + 1] + u5[l]);
+  if (sl < sr) left = left + 1;
+  return left;
+}
+
+/* ENO value of cell i at x_{i+1/2} (v^-) and at x_{i-1/2} (v^+) from the chosen stencil S_r:
+ * Table 3 row r at x_{i+1/2} and row r-1 at x_{i-1/2}, each perturbed with its interface's eta
+ * (eta = 0 gives the regular ENO scheme). */
+double npo_eno_minus(const double u5[5], double eta_right) {
+  int r = npo_eno_stencil(u5);
+  return npo_row_value(r, u5[2 - r], u5[3 - r], u5[4 - r], eta_right);
+}
+double npo_eno_plus(const double u5[5], double eta_left) {
+  int r = npo_eno_stencil(u5);
+  return npo_row_value(r - 1, u5[2 - r], u5[3 - r], u5[4 - r], eta_left);
+}
+
+/* ------------------------------------------------------------------------------------ */
 /* Physical fluxes and spectral radii (Section 5.1; Example 4 for Euler).                 */
 /* ------------------------------------------------------------------------------------ */
 static void phys_flux(const npo_problem* pb, int dir, const double* U, double* F) {
@@ -246,7 +279,7 @@ void npo_line_states(const npo_problem* pb, const double* line, long n, double* 
     /* interface x_{i+1/2}, stored at index i+1 */
     double eta = 0.0;
     int flag = 0;
-    if (pb->recon == NPO_RBF_WENO5) {
+    if (pb->recon == NPO_RBF_WENO5 || pb->recon == NPO_RBF_ENO3) {
       eta = npo_eta(G(i - 1), G(i), G(i + 1), G(i + 2), pb->eps_m);
       if (pb->switch_mode == NPO_SWITCH_MONOTONE) {
         /* Reading (k = 3 switch): the interface's eta vanishes when either 3-cell window
@@ -261,8 +294,13 @@ void npo_line_states(const npo_problem* pb, const double* line, long n, double* 
       uL[k] = G(i - 2 + k); /* cells i-2..i+2: v^- of cell i */
       uR[k] = G(i - 1 + k); /* cells i-1..i+3: v^+ of cell i+1 */
     }
-    vminus[i + 1] = npo_recon_minus(uL, eta, pb->eps_weno);
-    vplus[i + 1] = npo_recon_plus(uR, eta, pb->eps_weno);
+    if (pb->recon == NPO_RBF_ENO3 || pb->recon == NPO_ENO3) {
+      vminus[i + 1] = npo_eno_minus(uL, eta);
+      vplus[i + 1] = npo_eno_plus(uR, eta);
+    } else {
+      vminus[i + 1] = npo_recon_minus(uL, eta, pb->eps_weno);
+      vplus[i + 1] = npo_recon_plus(uR, eta, pb->eps_weno);
+    }
     if (eta_out) eta_out[i + 1] = eta;
     if (flag_out) flag_out[i + 1] = flag;
   }
@@ -284,7 +322,7 @@ static int validate(const npo_problem* pb) {
   if (pb->bc != NPO_PERIODIC && pb->bc != NPO_TRANSMISSIVE) return NPO_EINVAL;
   if (!(pb->x1 > pb->x0) || (pb->dim == 2 && !(pb->y1 > pb->y0))) return NPO_EINVAL;
   if (!(pb->cfl > 0.0) || !(pb->eps_weno > 0.0) || !(pb->eps_m > 0.0)) return NPO_EINVAL;
-  if (pb->recon != NPO_RBF_WENO5 && pb->recon != NPO_WENO5_JS) return NPO_EINVAL;
+  if (pb->recon < NPO_RBF_WENO5 || pb->recon > NPO_ENO3) return NPO_EINVAL;
   if (pb->switch_mode != NPO_SWITCH_MONOTONE && pb->switch_mode != NPO_SWITCH_OFF) return NPO_EINVAL;
   return NPO_OK;
 }

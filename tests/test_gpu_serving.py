@@ -37,7 +37,7 @@ def test_results_identical_alone_and_in_the_mix(prec):
     _say(f"serving mix prec={prec}")
     ws = _requests(14, seed=4, nmax=6000, tmax=0.15)
     esize = 4 if prec == B.FP32 else 8
-    budget = 3 * esize * 14000  # admission binds: the arena holds ~14k elements
+    budget = 3 * esize * 24000  # the arena holds 24k elements: a few requests at a time (Euler N=6000 is 18k)
     with B.Server(budget, max_slots=3, precision=prec) as srv:
         ids = [srv.submit(w.u0, w.T, **B.workload_params(w, prec)) for w in ws]
         saw_queue = _drain(srv, ids)

@@ -280,3 +280,66 @@ def test_2d_linear_advection_high_order():
         errs.append(O.errors(u, avg(0.25).reshape(-1))[0])
     orders = [math.log2(errs[k] / errs[k + 1]) for k in range(2)]
     assert min(orders) > 4.3, (errs, orders)
+
+
+# ---------------------------------------------------------------------------------------
+# ENO and RBF-ENO, k = 3 (Table 5): stencil choice by divided differences, same eta and switch
+# ---------------------------------------------------------------------------------------
+_T5E = load_golden("table5_eno_k3.txt")
+
+
+def _eno_errors(n, recon, switch):
+    h = 2.0 / n
+    pb = O.Problem(nx=n, flux=O.ADVECTION, cfl=0.1, recon=recon, switch_mode=switch, dt_fixed=0.1 * h)
+    u, _, _ = O.solve(pb, I.sine_cell_averages(n), 0.5)
+    return O.errors(u, I.sine_cell_averages(n, phase=-0.5 * math.pi))
+
+
+@pytest.mark.parametrize("row", _T5E, ids=[f"{r[0]}-{r[1]}" for r in _T5E])
+def test_table5_eno_rows(row):
+    method, n, l1, l2, linf = row
+    if method == "ENO":
+        g1, g2, ginf = _eno_errors(n, O.ENO3, O.SWITCH_OFF)
+        if n >= 80:
+            assert g1 == pytest.approx(l1, rel=0.03) and ginf == pytest.approx(linf, rel=0.03)
+        elif n >= 20:
+            assert g1 == pytest.approx(l1, rel=0.10)
+    else:
+        g1, g2, ginf = _eno_errors(n, O.RBF_ENO3, O.SWITCH_MONOTONE)
+        if n == 320:
+            assert g1 == pytest.approx(l1, rel=0.03) and ginf == pytest.approx(linf, rel=0.01)
+        elif n >= 20:
+            assert g1 == pytest.approx(l1, rel=0.25)
+
+
+def test_rbf_eno_needs_the_switch_at_n320():
+    g1, _, _ = _eno_errors(320, O.RBF_ENO3, O.SWITCH_OFF)
+    assert g1 > 5 * 2.76e-8
+
+
+def test_rbf_eno_one_order_above_eno():
+    """Section 8: RBF-ENO improves ENO's third order to about fourth order (k = 3)."""
+    e = [_eno_errors(n, O.RBF_ENO3, O.SWITCH_MONOTONE)[0] for n in (80, 160, 320)]
+    f = [_eno_errors(n, O.ENO3, O.SWITCH_OFF)[0] for n in (80, 160, 320)]
+    assert math.log2(e[1] / e[2]) > 3.8 and math.log2(f[1] / f[2]) < 3.1
+
+
+def test_eno_stencil_is_the_smoothest():
+    """On a step the chosen stencil never crosses the jump; on smooth data it follows the
+    smaller divided differences; ties go to the right."""
+    assert O.eno_stencil([0, 0, 0, 1, 1]) == 2  # jump right of cell i: take {i-2, i-1, i}
+    assert O.eno_stencil([0, 0, 1, 1, 1]) == 0  # jump left of cell i: take {i, i+1, i+2}
+    assert O.eno_stencil([1, 1, 1, 1, 1]) == 0  # all ties: rightmost
+    assert O.eno_stencil([0, 1, 4, 9, 16]) in (0, 1, 2)
+
+
+def test_eno_exact_for_quadratics():
+    """Every 3-cell stencil reproduces a quadratic, so the ENO edge values equal the point
+    values whichever stencil is chosen (eta = 0)."""
+    rng = np.random.default_rng(12)
+    for _ in range(20):
+        a, b, c = rng.normal(size=3)
+        # cell averages on unit cells [m, m+1], m = -2..2, of a x^2 + b x + c
+        u5 = np.array([a * (m * m + m + 1.0 / 3.0) + b * (m + 0.5) + c for m in range(-2, 3)])
+        assert O.eno_minus(u5, 0.0) == pytest.approx(a + b + c, abs=1e-12)  # x = 1
+        assert O.eno_plus(u5, 0.0) == pytest.approx(c, abs=1e-12)  # x = 0
