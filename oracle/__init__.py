@@ -25,6 +25,7 @@ _LIB = os.path.join(_HERE, "libnpw_oracle.so")
 ADVECTION, BURGERS, EULER = 0, 1, 2
 PERIODIC, TRANSMISSIVE = 0, 1
 RBF_WENO5, WENO5_JS, RBF_ENO3, ENO3 = 0, 1, 2, 3
+RBF_WENO3, WENO3_JS, RBF_ENO2, ENO2 = 4, 5, 6, 7
 SWITCH_MONOTONE, SWITCH_OFF = 0, 1
 OK, EINVAL, ENONFINITE, ENONPHYSICAL = 0, -1, -4, -5
 
@@ -116,6 +117,10 @@ def lib():
         L.npo_eno_minus.restype = ctypes.c_double
         L.npo_eno_plus.argtypes = [_D, ctypes.c_double]
         L.npo_eno_plus.restype = ctypes.c_double
+        L.npo_row2_value.argtypes = [ctypes.c_int] + [ctypes.c_double] * 3
+        L.npo_row2_value.restype = ctypes.c_double
+        L.npo_eta2.argtypes = [ctypes.c_double] * 4
+        L.npo_eta2.restype = ctypes.c_double
         L.npo_line_states.argtypes = [P, _D, ctypes.c_long, _D, _D, _D, _I]
         L.npo_alpha.argtypes = [P, _D, _D]
         L.npo_alpha.restype = ctypes.c_int
@@ -184,6 +189,14 @@ def eno_minus(u5, eta_right) -> float:
 
 def eno_plus(u5, eta_left) -> float:
     return lib().npo_eno_plus(_dp(_f64(u5)), eta_left)
+
+
+def row2_value(r: int, w0: float, w1: float, eta: float) -> float:
+    return lib().npo_row2_value(r, w0, w1, eta)
+
+
+def eta2(um1, u0, up1, eps_m=1e-12) -> float:
+    return lib().npo_eta2(um1, u0, up1, eps_m)
 
 
 def line_states(pb: Problem, line):

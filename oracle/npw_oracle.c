@@ -194,6 +194,86 @@ double npo_eno_plus(const double u5[5], double eta_left) {
 }
 
 /* ------------------------------------------------------------------------------------ */
+/* k = 2 (Sections 3.1-3.2, Table 2).                                                     */
+/* Row r (r = -1, 0, 1) reconstructs the value at x_{i+1/2} from (ubar_{i-r}, ubar_{i-r+1}):  */
+/* polynomial part (Table 2 left) plus eta times the multiquadric perturbation (right).     */
+/* ------------------------------------------------------------------------------------ */
+static const double TAB2_C[3][2] = {
+    /* r = -1 */ {3.0 / 2.0, -1.0 / 2.0},
+    /* r =  0 */ {1.0 / 2.0, 1.0 / 2.0},
+    /* r =  1 */ {-1.0 / 2.0, 3.0 / 2.0},
+};
+static const double TAB2_P[3][2] = {
+    /* r = -1 */ {-3.0 / 2.0, 1.0 / 2.0},
+    /* r =  0 */ {1.0 / 4.0, 1.0 / 4.0},
+    /* r =  1 */ {1.0 / 2.0, -3.0 / 2.0},
+};
+
+double npo_row2_value(int r, double w0, double w1, double eta) {
+  const double* c = TAB2_C[r + 1];
+  const double* p = TAB2_P[r + 1];
+  return (c[0] + eta * p[0]) * w0 + (c[1] + eta * p[1]) * w1;
+}
+
+/* Shape parameter of cell i for its right edge, Table 2 caption (from eq. i+1/2_eps_approx):
+ *     eta = 2 (-u_{i-1} + 2 u_i - u_{i+1}) / (-u_{i-1} + 5 u_i + 2 u_{i+1} + eps_M),
+ * the ratio of the second difference to six times the estimate of v(x_{i+1/2}).  The left edge
+ * uses the mirror image (u_{i-1} and u_{i+1} exchanged).  Reading: eps_M carries the sign of
+ * the denominator, as for k = 3. */
+double npo_eta2(double um1, double u0, double up1, double eps_m) {
+  double num = 2.0 * (-um1 + 2.0 * u0 - up1);
+  double den = -um1 + 5.0 * u0 + 2.0 * up1;
+  if (den >= 0.0)
+    den = den + eps_m;
+  else
+    den = den - eps_m;
+  return num / den;
+}
+
+/* WENO3 values of cell i (window u3 = u_{i-1}, u_i, u_{i+1}): v^-_{i+1/2} combines row 0 on
+ * {i, i+1} and row 1 on {i-1, i} with linear weights 2/3, 1/3; v^+_{i-1/2} combines row -1 on
+ * {i, i+1} and row 0 on {i-1, i} with 1/3, 2/3.  Smoothness indicators (Jiang-Shu, k = 2):
+ * beta_0 = (u_{i+1} - u_i)^2, beta_1 = (u_i - u_{i-1})^2; alpha_r = d_r / (eps + beta_r)^2. */
+static void weno3_weights(const double d[2], double b0, double b1, double eps, double w[2]) {
+  double a0 = d[0] / ((eps + b0) * (eps + b0));
+  double a1 = d[1] / ((eps + b1) * (eps + b1));
+  double s = a0 + a1;
+  w[0] = a0 / s;
+  w[1] = a1 / s;
+}
+double npo_weno3_minus(const double u3[3], double eta, double eps) {
+  static const double d[2] = {2.0 / 3.0, 1.0 / 3.0};
+  double t, b0, b1, w[2];
+  t = u3[2] - u3[1];
+  b0 = t * t;
+  t = u3[1] - u3[0];
+  b1 = t * t;
+  weno3_weights(d, b0, b1, eps, w);
+  return w[0] * npo_row2_value(0, u3[1], u3[2], eta) + w[1] * npo_row2_value(1, u3[0], u3[1], eta);
+}
+double npo_weno3_plus(const double u3[3], double eta, double eps) {
+  static const double d[2] = {1.0 / 3.0, 2.0 / 3.0};
+  double t, b0, b1, w[2];
+  t = u3[2] - u3[1];
+  b0 = t * t;
+  t = u3[1] - u3[0];
+  b1 = t * t;
+  weno3_weights(d, b0, b1, eps, w);
+  return w[0] * npo_row2_value(-1, u3[1], u3[2], eta) + w[1] * npo_row2_value(0, u3[0], u3[1], eta);
+}
+/* ENO, k = 2 (Section 3): {i-1, i} when its undivided difference is strictly smaller, else
+ * {i, i+1}; returns r (0: {i, i+1}, 1: {i-1, i}). */
+int npo_eno2_stencil(const double u3[3]) { return fabs(u3[1] - u3[0]) < fabs(u3[2] - u3[1]) ? 1 : 0; }
+double npo_eno2_minus(const double u3[3], double eta) {
+  int r = npo_eno2_stencil(u3);
+  return npo_row2_value(r, u3[1 - r], u3[2 - r], eta);
+}
+double npo_eno2_plus(const double u3[3], double eta) {
+  int r = npo_eno2_stencil(u3);
+  return npo_row2_value(r - 1, u3[1 - r], u3[2 - r], eta);
+}
+
+/* ------------------------------------------------------------------------------------ */
 /* Physical fluxes and spectral radii (Section 5.1; Example 4 for Euler).                 */
 /* ------------------------------------------------------------------------------------ */
 static void phys_flux(const npo_problem* pb, int dir, const double* U, double* F) {
@@ -271,8 +351,48 @@ static long ghost(long i, long n, int bc) {
 /* i = -1..n-1 (stored at index i+1), compute eta, the switch, v^- (from cell i) and v^+   */
 /* (from cell i+1).  line[] holds the n cell averages of one component; ghosts follow bc. */
 /* ------------------------------------------------------------------------------------ */
+static int is_k2(int recon) { return recon >= NPO_RBF_WENO3; }
+
+/* k = 2 interface states: cell i gives v^-_{i+1/2} with its right-edge eta and cell i+1 gives
+ * v^+_{i+1/2} with its left-edge eta; the Section 4 switch (stated for k = 2) zeroes both etas of
+ * a cell whose window {i-1, i, i+1} is not monotone. */
+static void line_states_k2(const npo_problem* pb, const double* line, long n, double* vminus, double* vplus,
+                           double* eta_out, int* flag_out) {
+#define G(k) line[ghost((k), n, pb->bc)]
+  const int rbf = pb->recon == NPO_RBF_WENO3 || pb->recon == NPO_RBF_ENO2;
+  const int weno = pb->recon == NPO_RBF_WENO3 || pb->recon == NPO_WENO3_JS;
+  for (long i = -1; i <= n - 1; ++i) {
+    double uL[3] = {G(i - 1), G(i), G(i + 1)};     /* cell i */
+    double uR[3] = {G(i), G(i + 1), G(i + 2)};     /* cell i+1 */
+    double eL = 0.0, eR = 0.0;
+    int flag = 0;
+    if (rbf) {
+      eL = npo_eta2(uL[0], uL[1], uL[2], pb->eps_m);  /* right edge of cell i */
+      eR = npo_eta2(uR[2], uR[1], uR[0], pb->eps_m);  /* left edge of cell i+1 (mirror) */
+      if (pb->switch_mode == NPO_SWITCH_MONOTONE) {
+        if (npo_monotone_flag(uL[0], uL[1], uL[2])) eL = 0.0, flag = 1;
+        if (npo_monotone_flag(uR[0], uR[1], uR[2])) eR = 0.0, flag = 1;
+      }
+    }
+    if (weno) {
+      vminus[i + 1] = npo_weno3_minus(uL, eL, pb->eps_weno);
+      vplus[i + 1] = npo_weno3_plus(uR, eR, pb->eps_weno);
+    } else {
+      vminus[i + 1] = npo_eno2_minus(uL, eL);
+      vplus[i + 1] = npo_eno2_plus(uR, eR);
+    }
+    if (eta_out) eta_out[i + 1] = eL;
+    if (flag_out) flag_out[i + 1] = flag;
+  }
+#undef G
+}
+
 void npo_line_states(const npo_problem* pb, const double* line, long n, double* vminus,
                      double* vplus, double* eta_out, int* flag_out) {
+  if (is_k2(pb->recon)) {
+    line_states_k2(pb, line, n, vminus, vplus, eta_out, flag_out);
+    return;
+  }
   /* G(k) = cell average of cell k (ghosts included), k = -3..n+2 */
 #define G(k) line[ghost((k), n, pb->bc)]
   for (long i = -1; i <= n - 1; ++i) {
@@ -322,7 +442,7 @@ static int validate(const npo_problem* pb) {
   if (pb->bc != NPO_PERIODIC && pb->bc != NPO_TRANSMISSIVE) return NPO_EINVAL;
   if (!(pb->x1 > pb->x0) || (pb->dim == 2 && !(pb->y1 > pb->y0))) return NPO_EINVAL;
   if (!(pb->cfl > 0.0) || !(pb->eps_weno > 0.0) || !(pb->eps_m > 0.0)) return NPO_EINVAL;
-  if (pb->recon < NPO_RBF_WENO5 || pb->recon > NPO_ENO3) return NPO_EINVAL;
+  if (pb->recon < NPO_RBF_WENO5 || pb->recon > NPO_ENO2) return NPO_EINVAL;
   if (pb->switch_mode != NPO_SWITCH_MONOTONE && pb->switch_mode != NPO_SWITCH_OFF) return NPO_EINVAL;
   return NPO_OK;
 }

@@ -12,7 +12,10 @@ extern "C" {
 enum { NPO_OK = 0, NPO_EINVAL = -1, NPO_ENONFINITE = -4, NPO_ENONPHYSICAL = -5 };
 enum { NPO_ADVECTION = 0, NPO_BURGERS = 1, NPO_EULER = 2 };
 enum { NPO_PERIODIC = 0, NPO_TRANSMISSIVE = 1 };
-enum { NPO_RBF_WENO5 = 0, NPO_WENO5_JS = 1, NPO_RBF_ENO3 = 2, NPO_ENO3 = 3 };
+enum {
+  NPO_RBF_WENO5 = 0, NPO_WENO5_JS = 1, NPO_RBF_ENO3 = 2, NPO_ENO3 = 3, /* k = 3 */
+  NPO_RBF_WENO3 = 4, NPO_WENO3_JS = 5, NPO_RBF_ENO2 = 6, NPO_ENO2 = 7  /* k = 2 */
+};
 enum { NPO_SWITCH_MONOTONE = 0, NPO_SWITCH_OFF = 1 };
 
 typedef struct {
@@ -25,7 +28,7 @@ typedef struct {
   double speed_x, speed_y; /* advection velocity */
   double gamma;            /* Euler ratio of specific heats */
   double cfl, eps_weno, eps_m;
-  int recon;       /* NPO_RBF_WENO5, NPO_WENO5_JS (eta = 0), NPO_RBF_ENO3, NPO_ENO3 (eta = 0) */
+  int recon;       /* NPO_* reconstruction (k = 3 or k = 2; the non-RBF ones have eta = 0) */
   int switch_mode; /* NPO_SWITCH_MONOTONE or NPO_SWITCH_OFF */
   double dt_fixed; /* > 0: fixed time step instead of the CFL rule */
 } npo_problem;
@@ -40,6 +43,13 @@ double npo_recon_plus(const double u5[5], double eta_left, double eps);
 int npo_eno_stencil(const double u5[5]);
 double npo_eno_minus(const double u5[5], double eta_right);
 double npo_eno_plus(const double u5[5], double eta_left);
+double npo_row2_value(int r, double w0, double w1, double eta);
+double npo_eta2(double um1, double u0, double up1, double eps_m);
+double npo_weno3_minus(const double u3[3], double eta, double eps);
+double npo_weno3_plus(const double u3[3], double eta, double eps);
+int npo_eno2_stencil(const double u3[3]);
+double npo_eno2_minus(const double u3[3], double eta);
+double npo_eno2_plus(const double u3[3], double eta);
 void npo_line_states(const npo_problem* pb, const double* line, long n, double* vminus,
                      double* vplus, double* eta_out, int* flag_out);
 int npo_alpha(const npo_problem* pb, const double* u, double alpha[2]);

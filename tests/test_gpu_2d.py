@@ -96,3 +96,14 @@ def test_euler2d_full_size_one_step():
     assert np.array_equal(u, uo)
     vo, _, _ = O.solve(_oracle_problem(w), u32.astype(np.float64), w.T, max_steps=1)
     assert np.max(np.abs(v - vo)) <= 1e-5
+
+
+@pytest.mark.parametrize("recon", [I.RBF_ENO3, I.WENO5_JS])
+def test_euler2d_other_reconstructions_fp64(recon):
+    _say(f"euler2d recon={recon}")
+    w = _quadrants(80, 80).with_(recon=recon)
+    with B.Solver(w.u0, **B.workload_params(w)) as s:
+        s.solve(w.T, max_steps=10)
+        u = s.read()
+    uo, _, _ = O.solve(_oracle_problem(w), w.u0, w.T, max_steps=10)
+    assert np.array_equal(u, uo)

@@ -63,7 +63,8 @@ def test_rhs_burgers_fp64(n, bc):
 
 
 @pytest.mark.parametrize("recon,sw", [(I.RBF_WENO5, I.SWITCH_MONOTONE), (I.RBF_WENO5, I.SWITCH_OFF),
-                                      (I.WENO5_JS, I.SWITCH_MONOTONE)])
+                                      (I.WENO5_JS, I.SWITCH_MONOTONE), (I.RBF_ENO3, I.SWITCH_MONOTONE),
+                                      (I.RBF_ENO3, I.SWITCH_OFF), (I.ENO3, I.SWITCH_MONOTONE)])
 def test_rhs_modes_fp64(recon, sw):
     _say(f"rhs modes recon={recon} sw={sw}")
     n = 777
@@ -328,3 +329,36 @@ def test_full_size_burgers_full_solve_conserves_fp64():
     # double evaluation of the scheme, the oracle's included, loses about 2^-54 of the cell-average
     # sum per step (46977 steps: 2.6e-12, as observed)
     assert abs(st["mass"][0] - m0) <= 4 * st["nsteps"] * 2.0 ** -53 * abs(m0)
+
+
+# ---------------------------------------------------------------------------------------
+# ENO / RBF-ENO reconstruction modes (stencil choice by divided differences)
+# ---------------------------------------------------------------------------------------
+@pytest.mark.parametrize("recon", [I.RBF_ENO3, I.ENO3])
+def test_eno_advection_table5_case_fp64(recon):
+    _say(f"eno advection N320 recon={recon}")
+    n = 320
+    w = I.advection_sine(n, T=0.5, cfl=0.1, recon=recon, dt_fixed=0.1 * 2.0 / n)
+    with _solver(w) as s:
+        st = s.solve(w.T)
+        u = s.read()
+    uo, _, no = O.solve(_oracle_problem(w), w.u0, w.T)
+    assert st["nsteps"] == no
+    assert np.array_equal(u, uo)
+    err = np.mean(np.abs(u - I.sine_cell_averages(n, phase=-0.5 * math.pi)))
+    assert err == pytest.approx(2.76e-8 if recon == I.RBF_ENO3 else 6.34e-7, rel=0.03)  # Table 5
+
+
+@pytest.mark.parametrize("prec", [B.FP64, B.FP32])
+def test_eno_euler_and_burgers(prec):
+    _say(f"eno euler/burgers prec={prec}")
+    for w in (I.sod(500, recon=I.RBF_ENO3), I.burgers_noisy(n=3000, seed=9, recon=I.RBF_ENO3)):
+        u0 = np.asarray(w.u0, np.float32 if prec == B.FP32 else np.float64)
+        with B.Solver(u0, **B.workload_params(w, prec)) as s:
+            s.solve(w.T, max_steps=80)
+            u = s.read().astype(np.float64)
+        uo, _, _ = O.solve(_oracle_problem(w), u0.astype(np.float64), w.T, max_steps=80)
+        if prec == B.FP64:
+            assert np.array_equal(u, uo)
+        else:
+            assert np.mean(np.abs(u - uo)) <= 1e-5

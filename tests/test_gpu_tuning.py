@@ -39,4 +39,4 @@ def test_autotuner_caches_and_block_size_never_changes_results(tmp_path, monkeyp
             with B.Solver(np.asarray(x.u0, np.float32), **B.workload_params(x, B.FP32)) as s:
                 s.solve(0.05)
                 assert np.array_equal(bt.read(b), s.read())
-    assert len(cache.read_text().split()) == 4
+    assert any(k.endswith("_i1") for k in cache.read_text().split()[::2])  # the batch got its own entry
