@@ -31,6 +31,7 @@ HBM_PEAK_GBS = 8000.0
 # Algorithmic HBM element accesses per cell, component and RK stage: stage 1 reads u^n and
 # writes u^(1); stages 2 and 3 read u^n and the stage input and write the output.
 ACCESSES_PER_CELL_STAGE = 8.0 / 3.0
+METRIC = "cell-updates/s per RK stage at stated L1 err vs FP64 oracle; p50/p99 solve latency"
 
 
 def parse():
@@ -56,30 +57,35 @@ def _percentiles(x):
 
 
 def _time_solves(solver, reset, T, steps, warmup, max_rk, stream):
+    """Wall time of `steps` reset+solve rounds, plus the GPU time of the solves alone: a pair of
+    events on the solver's stream brackets each solve(), so the state reset is not counted."""
     import torch
     for _ in range(warmup):
         reset()
         solver.solve(T, max_rk)
     torch.cuda.synchronize()
     lat = []
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
+    evs = []
     t0 = time.perf_counter()
-    ev0.record(stream)
     rk = 0
     for _ in range(steps):
         a = time.perf_counter()
         reset()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
         st = solver.solve(T, max_rk)
+        e1.record(stream)
+        evs.append((e0, e1))
         lat.append(time.perf_counter() - a)
         rk = st["nsteps"]
-    ev1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    return wall, ev0.elapsed_time(ev1) / 1e3, lat, rk
+    gpu_s = sum(e0.elapsed_time(e1) for e0, e1 in evs) / 1e3
+    return wall, gpu_s, lat, rk
 
 
-def bench_single(args, w, prec, label):
+def bench_single(args, w, prec):
     """A single grid (1D or 2D) solved from its initial state `steps` times."""
     import torch
 
@@ -88,6 +94,12 @@ def bench_single(args, w, prec, label):
     u0_dev = torch.tensor(w.u0, dtype=tdt, device="cuda")
     stream = torch.cuda.Stream()
     solver = B.Solver(u0_dev, stream=stream.cuda_stream, **B.workload_params(w, prec))
+    shape = solver.launch_shape()
+    R = "float" if prec == B.FP32 else "double"
+    if w.dim == 1:
+        label = f"stage1d_kernel<{R}, Burgers, 1, {shape['block']}>"
+    else:
+        label = f"stage2d_kernel<{R}, Euler, 4, {shape['tile_x']}, {shape['tile_y']}>"
     wall, gpu_s, lat, rk = _time_solves(solver, lambda: solver.write(u0_dev, 0.0), w.T, args.steps, args.warmup,
                                         args.max_rk_steps, stream)
     ncell = w.ncell
@@ -106,6 +118,7 @@ def bench_single(args, w, prec, label):
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "kernel": label, "avg_launch_us": avg_launch * 1e6,
                      "bytes_per_launch": bytes_per_launch},
+        "launch_shape": shape,
     }
     return out, solver, u0_dev
 
@@ -160,21 +173,23 @@ def bench_batch(args, prec):
         bt.solve(T, args.max_rk_steps)
     torch.cuda.synchronize()
     lat = []
+    evs = []
     t0 = time.perf_counter()
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    ev0.record(stream)
     total_cell_stages = 0.0
     for _ in range(args.steps):
         a = time.perf_counter()
         reset()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
         stats, rc = bt.solve(T, args.max_rk_steps)
+        e1.record(stream)
+        evs.append((e0, e1))
         lat.append(time.perf_counter() - a)
         total_cell_stages += sum(w.nx * 3.0 * s["nsteps"] for w, s in zip(ws, stats))
-    ev1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    gpu_s = ev0.elapsed_time(ev1) / 1e3
+    gpu_s = sum(e0.elapsed_time(e1) for e0, e1 in evs) / 1e3
     max_steps = max(s["nsteps"] for s in stats)
     esize = 4 if prec == B.FP32 else 8
     achieved = ACCESSES_PER_CELL_STAGE * esize * 3 * total_cell_stages / gpu_s / 1e9
@@ -212,7 +227,7 @@ def bench_serving(args, prec):
     for r in trace:
         out, st, rc = srv.poll(ids[r.rid])
         a, b, c = srv.times(ids[r.rid])
-        lat.append(c - (a - (a - t0 - r.arrival)) if False else (c - t0) - r.arrival)
+        lat.append((c - t0) - r.arrival)
         nsteps[r.rid] = st["nsteps"]
         work += r.work.nx * 3.0 * st["nsteps"]
     srv.close()
@@ -252,18 +267,16 @@ def main():
     if args.workload in ("burgers", "euler2d"):
         if args.workload == "burgers":
             w = I.burgers_noisy(n=args.n or 65536, seed=2)
-            metric = ("cell-updates/s per RK stage (1D Burgers N=65536, RBF-WENO5 + monotone switch, "
-                      "global LF, SSP-RK3 CFL 0.5 to T=1.5/pi)")
-            label = f"stage1d_kernel<{'float' if prec == B.FP32 else 'double'}, Burgers, 1, 256>"
+            desc = ("1D Burgers N=65536 periodic, u0 = 0.5 + sin(pi x) + seeded noise 1e-3, RBF-WENO5 with the "
+                    "monotone switch, global LF, SSP-RK3 CFL 0.5 to T=1.5/pi")
         else:
             w = I.euler2d_quadrants(n=args.n or 2048)
-            metric = "cell-updates/s per RK stage (2D Euler 2048^2 four-quadrant, dimension by dimension, CFL 0.4 to T=0.25)"
-            label = f"stage2d_kernel<{'float' if prec == B.FP32 else 'double'}, Euler, 4, 64, 8>"
-        res, solver, u0_dev = bench_single(args, w, prec, label)
-        out = {"metric": metric, "value": res["value"], **base, "ms_per_step": res["ms_per_step"],
-               "config": {"workload": w.name, "cells": w.ncell, "T": w.T, "cfl": w.cfl,
+            desc = "2D Euler 2048^2 four-quadrant Riemann data, dimension by dimension, CFL 0.4 to T=0.25"
+        res, solver, u0_dev = bench_single(args, w, prec)
+        out = {"metric": METRIC, "value": res["value"], **base, "ms_per_step": res["ms_per_step"],
+               "config": {"workload": w.name, "description": desc, "cells": w.ncell, "T": w.T, "cfl": w.cfl,
                           "rk_steps_per_solve": res["rk_steps_per_solve"], "eta_precision": "f64",
-                          "block": int(os.environ.get("NPW_BLOCK", "256"))},
+                          "launch_shape": res["launch_shape"]},
                "latency_s": res["latency_s"], "roofline": res["roofline"]}
         if args.max_rk_steps >= 0:
             out["note"] = "profiling run: solves stopped after --max-rk-steps; not a benchmark value"
@@ -274,14 +287,16 @@ def main():
         solver.close()
     elif args.workload == "euler_batch":
         res = bench_batch(args, prec)
-        out = {"metric": "cell-updates/s per RK stage (4096 1D Euler Riemann problems, N in [256,4096], T=0.2)",
+        out = {"metric": METRIC,
                "value": res["value"], **base, "ms_per_step": res["ms_per_step"],
-               "config": {"workload": "euler_riemann_batch_4096", "instances": res["instances"],
+               "config": {"workload": "euler_riemann_batch_4096",
+                          "description": "4096 1D Euler Riemann problems, N in [256,4096], CFL 0.5 to T=0.2",
+                          "instances": res["instances"],
                           "cells": res["cells"], "max_rk_steps": res["max_rk_steps"]},
                "latency_s": res["latency_s"], "roofline": res["roofline"]}
     else:
         res = bench_serving(args, prec)
-        out = {"metric": "cell-updates/s per RK stage, serving (Poisson arrivals, mixed advection/Burgers/Euler)",
+        out = {"metric": METRIC,
                "value": res["value"], **base, "ms_per_step": None,
                "config": {"workload": "serving_trace", "requests": res["requests"], "trace": res["trace"]},
                "latency_s": res["latency_s"], "one_at_a_time": res["one_at_a_time"], "wall_s": res["wall_s"]}

@@ -56,7 +56,10 @@ enum {
 enum { NPW_ADVECTION = 0, NPW_BURGERS = 1, NPW_EULER = 2 };  /* flux type */
 enum { NPW_PERIODIC = 0, NPW_TRANSMISSIVE = 1 };             /* boundary, all sides */
 enum { NPW_FP64 = 0, NPW_FP32 = 1 };  /* bulk precision; eta, the switch test, dt and t are always FP64 */
-enum { NPW_RBF_WENO5 = 0, NPW_WENO5_JS = 1 };                /* WENO5_JS: eta forced to zero */
+/* Reconstruction (k = 3): RBF-WENO5 (the hot path), WENO5-JS (eta forced to zero), RBF-ENO3 (one
+ * stencil chosen by Newton divided differences, Section 2, perturbed with the same eta and
+ * switch) and ENO3 (its eta = 0 limit). */
+enum { NPW_RBF_WENO5 = 0, NPW_WENO5_JS = 1, NPW_RBF_ENO3 = 2, NPW_ENO3 = 3 };
 enum { NPW_SWITCH_MONOTONE = 0, NPW_SWITCH_OFF = 1 };        /* Section 4 switch on / off */
 
 typedef struct {
@@ -66,7 +69,7 @@ typedef struct {
   int32_t ncomp;       /* 1 for scalar fluxes, 3 for 1D Euler, 4 for 2D Euler */
   int32_t bc;          /* NPW_PERIODIC or NPW_TRANSMISSIVE (copy of the edge cell) */
   int32_t precision;   /* NPW_FP64 or NPW_FP32 */
-  int32_t recon;       /* NPW_RBF_WENO5 or NPW_WENO5_JS */
+  int32_t recon;       /* NPW_RBF_WENO5, NPW_WENO5_JS, NPW_RBF_ENO3 or NPW_ENO3 */
   int32_t switch_mode; /* NPW_SWITCH_MONOTONE or NPW_SWITCH_OFF */
   int64_t nx, ny;      /* cells per direction; ny is ignored (treated as 1) in 1D */
   double x0, x1, y0, y1;   /* domain; y0, y1 ignored in 1D */
@@ -150,6 +153,11 @@ int npweno_solve_batch(npw_solver* s, const double* t_final, int64_t max_steps, 
 int npweno_read_instance(const npw_solver* s, int32_t index, void* u_out, int out_on_device);
 int npweno_get_stats_instance(const npw_solver* s, int32_t index, npw_stats* stats);
 int npweno_instance_count(const npw_solver* s);
+/* Launch shape the solver uses for its stage kernel (picked at create by the autotuner, or set by
+ * NPW_BLOCK / NPW_TILE2D): *block_1d = threads per workgroup of the 1D kernel (128, 256 or 512),
+ * *tile_x, *tile_y = interior cells per workgroup of the 2D kernel (0 for a 1D solver).  Any
+ * output pointer may be NULL.  Host-only; returns NPW_EINVAL for a NULL solver. */
+int npweno_launch_shape(const npw_solver* s, int32_t* block_1d, int32_t* tile_x, int32_t* tile_y);
 
 /* ---- Serving (continuous batching) -------------------------------------------------------- */
 /* A request loop for mixed 1D solves.  All requests share one device arena of

@@ -19,7 +19,7 @@ OK, EINVAL, ENOMEM, EHIP, ENONFINITE, ENONPHYSICAL, EBUSY, ENOTFOUND = 0, -1, -2
 ADVECTION, BURGERS, EULER = 0, 1, 2
 PERIODIC, TRANSMISSIVE = 0, 1
 FP64, FP32 = 0, 1
-RBF_WENO5, WENO5_JS = 0, 1
+RBF_WENO5, WENO5_JS, RBF_ENO3, ENO3 = 0, 1, 2, 3
 SWITCH_MONOTONE, SWITCH_OFF = 0, 1
 
 
@@ -92,6 +92,8 @@ def lib():
         L.npweno_get_stats_instance.argtypes = [_VP, ctypes.c_int32, S]
         L.npweno_instance_count.argtypes = [_VP]
         L.npweno_instance_count.restype = ctypes.c_int
+        I32P = ctypes.POINTER(ctypes.c_int32)
+        L.npweno_launch_shape.argtypes = [_VP, I32P, I32P, I32P]
         U64 = ctypes.c_uint64
         L.npw_server_create.argtypes = [ctypes.c_size_t, ctypes.c_int32, ctypes.c_int32, _VP, ctypes.POINTER(_VP)]
         L.npw_server_submit.argtypes = [_VP, P, _VP, ctypes.c_double, ctypes.POINTER(U64)]
@@ -206,6 +208,13 @@ class Solver:
         st = Stats()
         _check(lib().npweno_get_stats(self.h, ctypes.byref(st)), "npweno_get_stats")
         return st.as_dict()
+
+    def launch_shape(self) -> dict:
+        """Stage-kernel launch shape in use: 1D threads per workgroup, 2D owned tile."""
+        b, tx, ty = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().npweno_launch_shape(self.h, ctypes.byref(b), ctypes.byref(tx), ctypes.byref(ty)),
+               "npweno_launch_shape")
+        return {"block": b.value, "tile_x": tx.value, "tile_y": ty.value}
 
     def close(self):
         if getattr(self, "h", None):

@@ -90,64 +90,120 @@ __device__ __forceinline__ R table3_row(R w0, R w1, R w2, R eta) {
            (R(11.0 / 6.0) + eta * R(-9.0 / 2.0)) * w2;
 }
 
-// Both reconstructed values of cell i from its five-cell window (a..e) = u_{i-2}..u_{i+2}:
-//   vm = v^-_{i+1/2} (rows 0, 1, 2 with eta_{i+1/2}, linear weights 3/10, 3/5, 1/10),
-//   vp = v^+_{i-1/2} (rows -1, 0, 1 with eta_{i-1/2}, linear weights 1/10, 3/5, 3/10),
-// combined with the nonlinear weights of eq. (weno_re), alpha_r = d_r / (eps + beta_r)^2.
-// Exact flavour: the operation order of the definition (alpha_r, then w_r = alpha_r / sum,
-// then sum w_r q_r).
-__device__ __forceinline__ void weno_pair_exact(double a, double b, double c, double d, double e,
-                                                double eta_r, double eta_l, double eps, bool want_m,
-                                                bool want_p, double& vm, double& vp) {
+// Weight denominators of cell i from its five-cell window (a..e) = u_{i-2}..u_{i+2}: the
+// exact flavour keeps s_r = (eps + beta_r)^2; the fast flavour keeps 1 / s_r.
+template <typename R>
+__device__ __forceinline__ void weight_denominators(R a, R b, R c, R d, R e, R eps, R& s0, R& s1, R& s2) {
+  R b0, b1, b2;
+  smoothness<R>(a, b, c, d, e, b0, b1, b2);
+  if constexpr (sizeof(R) == 8) {
 #pragma clang fp contract(off)
-  double b0, b1, b2;
-  smoothness<double>(a, b, c, d, e, b0, b1, b2);
-  const double s0 = (eps + b0) * (eps + b0), s1 = (eps + b1) * (eps + b1), s2 = (eps + b2) * (eps + b2);
-  if (want_m) {
-    double q0 = table3_row<double, 0>(c, d, e, eta_r);
-    double q1 = table3_row<double, 1>(b, c, d, eta_r);
-    double q2 = table3_row<double, 2>(a, b, c, eta_r);
-    double a0 = (3.0 / 10.0) / s0, a1 = (3.0 / 5.0) / s1, a2 = (1.0 / 10.0) / s2;
-    double s = a0 + a1 + a2;
-    double w0 = a0 / s, w1 = a1 / s, w2 = a2 / s;
-    vm = w0 * q0 + w1 * q1 + w2 * q2;
-  }
-  if (want_p) {
-    double q0 = table3_row<double, -1>(c, d, e, eta_l);
-    double q1 = table3_row<double, 0>(b, c, d, eta_l);
-    double q2 = table3_row<double, 1>(a, b, c, eta_l);
-    double a0 = (1.0 / 10.0) / s0, a1 = (3.0 / 5.0) / s1, a2 = (3.0 / 10.0) / s2;
-    double s = a0 + a1 + a2;
-    double w0 = a0 / s, w1 = a1 / s, w2 = a2 / s;
-    vp = w0 * q0 + w1 * q1 + w2 * q2;
+    s0 = (eps + b0) * (eps + b0);
+    s1 = (eps + b1) * (eps + b1);
+    s2 = (eps + b2) * (eps + b2);
+  } else {
+    const R g0 = eps + b0, g1 = eps + b1, g2 = eps + b2;
+    s0 = __builtin_amdgcn_rcpf(g0 * g0);
+    s1 = __builtin_amdgcn_rcpf(g1 * g1);
+    s2 = __builtin_amdgcn_rcpf(g2 * g2);
   }
 }
 
-// Fast float flavour: one reciprocal per (eps + beta_r)^2 shared by both sides, normalisation
-// by one reciprocal per side, and the perturbation split off as eta * (sum_j p_rj w_j).
-__device__ __forceinline__ void weno_pair_fast(float a, float b, float c, float d, float e, float eta_r,
-                                               float eta_l, float eps, bool want_m, bool want_p, float& vm,
-                                               float& vp) {
-  float b0, b1, b2;
-  smoothness<float>(a, b, c, d, e, b0, b1, b2);
-  const float g0 = eps + b0, g1 = eps + b1, g2 = eps + b2;
-  const float i0 = __builtin_amdgcn_rcpf(g0 * g0);
-  const float i1 = __builtin_amdgcn_rcpf(g1 * g1);
-  const float i2 = __builtin_amdgcn_rcpf(g2 * g2);
-  if (want_m) {
-    float q0 = table3_row<float, 0>(c, d, e, eta_r);
-    float q1 = table3_row<float, 1>(b, c, d, eta_r);
-    float q2 = table3_row<float, 2>(a, b, c, eta_r);
-    float a0 = 0.3f * i0, a1 = 0.6f * i1, a2 = 0.1f * i2;
-    vm = (a0 * q0 + a1 * q1 + a2 * q2) * __builtin_amdgcn_rcpf(a0 + a1 + a2);
+// v^-_{i+1/2} of cell i (Table 3 rows 0, 1, 2 with the interface's eta, linear weights 3/10, 3/5,
+// 1/10) and v^+_{i-1/2} of cell i (rows -1, 0, 1 with that interface's eta, linear weights 1/10,
+// 3/5, 3/10), combined with the nonlinear weights of eq. (weno_re), alpha_r = d_r / s_r.
+// (a..e) = u_{i-2}..u_{i+2}; (s0, s1, s2) from weight_denominators of the same cell.
+// Exact flavour: the operation order of the definition (alpha_r, w_r = alpha_r / sum, sum w_r q_r).
+__device__ __forceinline__ double weno_minus_exact(double a, double b, double c, double d, double e, double eta,
+                                                   double s0, double s1, double s2) {
+#pragma clang fp contract(off)
+  double q0 = table3_row<double, 0>(c, d, e, eta);
+  double q1 = table3_row<double, 1>(b, c, d, eta);
+  double q2 = table3_row<double, 2>(a, b, c, eta);
+  double a0 = (3.0 / 10.0) / s0, a1 = (3.0 / 5.0) / s1, a2 = (1.0 / 10.0) / s2;
+  double s = a0 + a1 + a2;
+  double w0 = a0 / s, w1 = a1 / s, w2 = a2 / s;
+  return w0 * q0 + w1 * q1 + w2 * q2;
+}
+__device__ __forceinline__ double weno_plus_exact(double a, double b, double c, double d, double e, double eta,
+                                                  double s0, double s1, double s2) {
+#pragma clang fp contract(off)
+  double q0 = table3_row<double, -1>(c, d, e, eta);
+  double q1 = table3_row<double, 0>(b, c, d, eta);
+  double q2 = table3_row<double, 1>(a, b, c, eta);
+  double a0 = (1.0 / 10.0) / s0, a1 = (3.0 / 5.0) / s1, a2 = (3.0 / 10.0) / s2;
+  double s = a0 + a1 + a2;
+  double w0 = a0 / s, w1 = a1 / s, w2 = a2 / s;
+  return w0 * q0 + w1 * q1 + w2 * q2;
+}
+// Fast float flavour: i_r = 1 / s_r precomputed, one reciprocal for the normalisation.
+__device__ __forceinline__ float weno_minus_fast(float a, float b, float c, float d, float e, float eta, float i0,
+                                                 float i1, float i2) {
+  const float q0 = table3_row<float, 0>(c, d, e, eta);
+  const float q1 = table3_row<float, 1>(b, c, d, eta);
+  const float q2 = table3_row<float, 2>(a, b, c, eta);
+  const float a0 = 0.3f * i0, a1 = 0.6f * i1, a2 = 0.1f * i2;
+  return (a0 * q0 + a1 * q1 + a2 * q2) * __builtin_amdgcn_rcpf(a0 + a1 + a2);
+}
+__device__ __forceinline__ float weno_plus_fast(float a, float b, float c, float d, float e, float eta, float i0,
+                                                float i1, float i2) {
+  const float q0 = table3_row<float, -1>(c, d, e, eta);
+  const float q1 = table3_row<float, 0>(b, c, d, eta);
+  const float q2 = table3_row<float, 1>(a, b, c, eta);
+  const float a0 = 0.1f * i0, a1 = 0.6f * i1, a2 = 0.3f * i2;
+  return (a0 * q0 + a1 * q1 + a2 * q2) * __builtin_amdgcn_rcpf(a0 + a1 + a2);
+}
+// ENO stencil of cell i from (a..e) = u_{i-2}..u_{i+2} (Section 2, Newton divided differences):
+// grow {i} twice towards the smaller undivided difference; ties keep the right-hand stencil.
+// Returns r with S_r(i) = {i-r, .., i-r+2}.  Double precision, uncontracted.
+__device__ __forceinline__ int eno_stencil(double a, double b, double c, double d, double e) {
+#pragma clang fp contract(off)
+  const double u[5] = {a, b, c, d, e};
+  int left = 0;
+  if (fabs(u[2] - u[1]) < fabs(u[3] - u[2])) left = 1;
+  const int l = 2 - left;
+  const double sl = fabs(u[l + 1] - 2.0 * u[l] + u[l - 1]);
+  const double sr = fabs(u[l + 2] - 2.0 * u[l + 1] + u[l]);
+  if (sl < sr) left = left + 1;
+  return left;
+}
+
+// Table 3 row `row` (-1..2) chosen at run time.
+template <typename R>
+__device__ __forceinline__ R table3_row_rt(int row, R w0, R w1, R w2, R eta) {
+  switch (row) {
+    case -1: return table3_row<R, -1>(w0, w1, w2, eta);
+    case 0: return table3_row<R, 0>(w0, w1, w2, eta);
+    case 1: return table3_row<R, 1>(w0, w1, w2, eta);
+    default: return table3_row<R, 2>(w0, w1, w2, eta);
   }
-  if (want_p) {
-    float q0 = table3_row<float, -1>(c, d, e, eta_l);
-    float q1 = table3_row<float, 0>(b, c, d, eta_l);
-    float q2 = table3_row<float, 1>(a, b, c, eta_l);
-    float a0 = 0.1f * i0, a1 = 0.6f * i1, a2 = 0.3f * i2;
-    vp = (a0 * q0 + a1 * q1 + a2 * q2) * __builtin_amdgcn_rcpf(a0 + a1 + a2);
-  }
+}
+
+// ENO edge values of a cell with stencil r, window (a..e): v^- uses row r, v^+ row r-1.
+template <typename R>
+__device__ __forceinline__ R eno_minus(int r, R a, R b, R c, R d, R e, R eta) {
+  const R w[5] = {a, b, c, d, e};
+  return table3_row_rt<R>(r, w[2 - r], w[3 - r], w[4 - r], eta);
+}
+template <typename R>
+__device__ __forceinline__ R eno_plus(int r, R a, R b, R c, R d, R e, R eta) {
+  const R w[5] = {a, b, c, d, e};
+  return table3_row_rt<R>(r - 1, w[2 - r], w[3 - r], w[4 - r], eta);
+}
+
+template <typename R>
+__device__ __forceinline__ R weno_minus(R a, R b, R c, R d, R e, R eta, R s0, R s1, R s2) {
+  if constexpr (sizeof(R) == 8)
+    return weno_minus_exact(a, b, c, d, e, eta, s0, s1, s2);
+  else
+    return weno_minus_fast(a, b, c, d, e, eta, s0, s1, s2);
+}
+template <typename R>
+__device__ __forceinline__ R weno_plus(R a, R b, R c, R d, R e, R eta, R s0, R s1, R s2) {
+  if constexpr (sizeof(R) == 8)
+    return weno_plus_exact(a, b, c, d, e, eta, s0, s1, s2);
+  else
+    return weno_plus_fast(a, b, c, d, e, eta, s0, s1, s2);
 }
 
 // Physical flux along direction DIR (0: x, 1: y) of the state U[0..M-1] (Section 5.1; Euler as in

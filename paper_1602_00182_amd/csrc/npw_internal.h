@@ -81,11 +81,15 @@ constexpr int kSpreadWords = 3 * 2 * kSpread * kSpreadStride;
 hipError_t launch_stage_f64(int flux, int ncomp, int block, const StageArgs& a, hipStream_t s);
 hipError_t launch_stage_f32(int flux, int ncomp, int block, const StageArgs& a, hipStream_t s);
 // Recompute alpha slot 0, finiteness/physicality checks and the per-component sums of u^n.
-hipError_t launch_stage2d_f64(int flux, int ncomp, const StageArgs& a, hipStream_t s);
-hipError_t launch_stage2d_f32(int flux, int ncomp, const StageArgs& a, hipStream_t s);
+// 2D tile shapes: 0 = 64 x 8, 1 = 62 x 8, 2 = 126 x 4 cells.
+constexpr int k2dShapes = 3;
+hipError_t launch_stage2d_f64(int flux, int ncomp, int shape, const StageArgs& a, hipStream_t s);
+hipError_t launch_stage2d_f32(int flux, int ncomp, int shape, const StageArgs& a, hipStream_t s);
+// scratch holds G * ninst partial records (kCheckPartialBytes each); G workgroups per instance.
+constexpr int kCheckPartialBytes = 56;
 hipError_t launch_init_f64(int flux, int ncomp, InstDev* inst, int ninst, void* P0, void* P1,
-                           unsigned long long* spread, hipStream_t s);
+                           unsigned long long* spread, void* scratch, int G, hipStream_t s);
 hipError_t launch_init_f32(int flux, int ncomp, InstDev* inst, int ninst, void* P0, void* P1,
-                           unsigned long long* spread, hipStream_t s);
+                           unsigned long long* spread, void* scratch, int G, hipStream_t s);
 
 }  // namespace npw

@@ -4,15 +4,15 @@
 // One workgroup owns a tile of BS-2 consecutive cells of one instance.  Thread t stands for cell
 // start-1+t, so the tile's interfaces x_{start-1/2} .. x_{start+BS-5/2} are all computed inside
 // the workgroup.  Phases (each followed by a barrier):
-//   load   -- cells start-3 .. start+BS (three ghosts per side) into LDS, coalesced, with
-//             periodic / transmissive ghost mapping;
-//   flag   -- Section 4 monotone test of the window centred on each cell (double);
-//   eta    -- Table 3 shape parameter of each interface (double), zeroed by the switch;
-//   recon  -- smoothness indicators of each cell, then v^-_{i+1/2} and v^+_{i-1/2} of that cell;
-//   flux   -- global Lax-Friedrichs flux of each interface;
-//   update -- flux difference (eq. PDE1), the SSP-RK3 stage combination, the store, and the
-//             epilogue: validity check and max wave speed of the new state (wave shuffles, one
-//             atomicMax per workgroup) that the next stage uses as its alpha.
+//   load      -- cells start-3 .. start+BS (three ghosts per side) into LDS, coalesced, with
+//                periodic / transmissive ghost mapping (issued before the control words are read);
+//   cell      -- Section 4 monotone test of the window centred on each cell (double) and the
+//                cell's three weight denominators (eps + beta_r)^2;
+//   interface -- Table 3 shape parameter (double) zeroed by the switch, v^- of the left cell,
+//                v^+ of the right cell, global Lax-Friedrichs flux;
+//   update    -- flux difference (eq. PDE1), the SSP-RK3 stage combination, the store, and the
+//                epilogue: validity check and max wave speed of the new state (DPP wave max, one
+//                atomicMax per workgroup) that the next stage uses as its alpha.
 #pragma once
 #include <type_traits>
 
@@ -27,9 +27,8 @@ __device__ __forceinline__ void stage1d_tile(const StageArgs& a, const Tile tile
   constexpr int W = BS + 4;  // LDS cells per component: start-3 .. start+BS
   __shared__ R s_u[M][W];
   __shared__ double s_d[kExact ? 1 : M][kExact ? 1 : W];
-  __shared__ int s_flag[M][BS];
-  __shared__ double s_eta[M][BS];
-  __shared__ R s_vp[M][BS];
+  __shared__ unsigned char s_flag[M][BS];
+  __shared__ R s_den[M][3][BS];
   __shared__ R s_F[M][BS];
   __shared__ unsigned long long s_red[BS / 64];
   __shared__ int s_bad[BS / 64];
@@ -135,7 +134,9 @@ __device__ __forceinline__ void stage1d_tile(const StageArgs& a, const Tile tile
   }
   const R alpha = R(bits_to_double(alpha_bits));
   const R rdt = R(dt);
-  const bool use_eta = (I->recon == NPW_RBF_WENO5);
+  const int recon = I->recon;
+  const bool eno = (recon == NPW_RBF_ENO3 || recon == NPW_ENO3);
+  const bool use_eta = (recon == NPW_RBF_WENO5 || recon == NPW_RBF_ENO3);
   const bool use_switch = use_eta && (I->sw == NPW_SWITCH_MONOTONE);
   const double eps_m = I->eps_m;
   const R eps = R(I->eps_weno);
@@ -164,49 +165,50 @@ __device__ __forceinline__ void stage1d_tile(const StageArgs& a, const Tile tile
       return s_d[c][idx];
   };
 
-  // ---- flag: window centred on cell start-1+tid (LDS index tid+2) -------------------------
-  if (use_switch) {
+  // ---- cell phase: cell start-1+tid (LDS window tid..tid+4) -------------------------------
+  // Section 4 monotone flag of the window centred on the cell, and the three weight
+  // denominators (eps + beta_r)^2 of the cell.
 #pragma unroll
-    for (int c = 0; c < M; ++c) s_flag[c][tid] = monotone_flag(D(c, tid + 1), D(c, tid + 2), D(c, tid + 3));
+  for (int c = 0; c < M; ++c) {
+    // bit 0: switch flag; bits 1-2: ENO stencil
+    int fl = use_switch ? monotone_flag(D(c, tid + 1), D(c, tid + 2), D(c, tid + 3)) : 0;
+    if (eno) {
+      fl |= eno_stencil(D(c, tid), D(c, tid + 1), D(c, tid + 2), D(c, tid + 3), D(c, tid + 4)) << 1;
+    } else {
+      R d0, d1, d2;
+      weight_denominators<R>(s_u[c][tid], s_u[c][tid + 1], s_u[c][tid + 2], s_u[c][tid + 3], s_u[c][tid + 4], eps,
+                             d0, d1, d2);
+      s_den[c][0][tid] = d0;
+      s_den[c][1][tid] = d1;
+      s_den[c][2][tid] = d2;
+    }
+    s_flag[c][tid] = (unsigned char)fl;
   }
   __syncthreads();
-  // ---- eta of interface x_{cell+1/2}, cells (LDS) tid+1 .. tid+4 ------------------------------
+  // ---- interface phase: x_{cell+1/2} between cell start-1+tid and the next (tid < BS-1) ----
+  // eta (Table 3 caption) zeroed by the switch, v^- of the left cell, v^+ of the right cell,
+  // and the global Lax-Friedrichs flux.
   if (tid < BS - 1) {
+    R A[M], B[M], H[M];
 #pragma unroll
     for (int c = 0; c < M; ++c) {
       double e = 0.0;
       if (use_eta) {
         e = eta_ratio(D(c, tid + 1), D(c, tid + 2), D(c, tid + 3), D(c, tid + 4), eps_m);
-        if (use_switch && (s_flag[c][tid] | s_flag[c][tid + 1])) e = 0.0;
+        if (use_switch && ((s_flag[c][tid] | s_flag[c][tid + 1]) & 1)) e = 0.0;
       }
-      s_eta[c][tid] = e;
-    }
-  }
-  __syncthreads();
-  // ---- recon: cell start-1+tid from LDS tid..tid+4 ----------------------------------------
-  R vm[M];
-#pragma unroll
-  for (int c = 0; c < M; ++c) {
-    const R eta_r = R(tid < BS - 1 ? s_eta[c][tid] : 0.0);
-    const R eta_l = R(tid > 0 ? s_eta[c][tid - 1] : 0.0);
-    R vp = R(0);
-    vm[c] = R(0);
-    if constexpr (kExact)
-      weno_pair_exact(s_u[c][tid], s_u[c][tid + 1], s_u[c][tid + 2], s_u[c][tid + 3], s_u[c][tid + 4], eta_r,
-                      eta_l, eps, tid < BS - 1, tid > 0, vm[c], vp);
-    else
-      weno_pair_fast(s_u[c][tid], s_u[c][tid + 1], s_u[c][tid + 2], s_u[c][tid + 3], s_u[c][tid + 4], eta_r,
-                     eta_l, eps, tid < BS - 1, tid > 0, vm[c], vp);
-    s_vp[c][tid] = vp;
-  }
-  __syncthreads();
-  // ---- flux at x_{cell+1/2} ---------------------------------------------------------------
-  if (tid < BS - 1) {
-    R A[M], B[M], H[M];
-#pragma unroll
-    for (int c = 0; c < M; ++c) {
-      A[c] = vm[c];
-      B[c] = s_vp[c][tid + 1];
+      const R eta = R(e);
+      if (eno) {
+        A[c] = eno_minus<R>(s_flag[c][tid] >> 1, s_u[c][tid], s_u[c][tid + 1], s_u[c][tid + 2], s_u[c][tid + 3],
+                            s_u[c][tid + 4], eta);
+        B[c] = eno_plus<R>(s_flag[c][tid + 1] >> 1, s_u[c][tid + 1], s_u[c][tid + 2], s_u[c][tid + 3],
+                           s_u[c][tid + 4], s_u[c][tid + 5], eta);
+      } else {
+        A[c] = weno_minus<R>(s_u[c][tid], s_u[c][tid + 1], s_u[c][tid + 2], s_u[c][tid + 3], s_u[c][tid + 4], eta,
+                             s_den[c][0][tid], s_den[c][1][tid], s_den[c][2][tid]);
+        B[c] = weno_plus<R>(s_u[c][tid + 1], s_u[c][tid + 2], s_u[c][tid + 3], s_u[c][tid + 4], s_u[c][tid + 5],
+                            eta, s_den[c][0][tid + 1], s_den[c][1][tid + 1], s_den[c][2][tid + 1]);
+      }
     }
     lf_flux<R, FLUX, M, 0>(A, B, alpha, speed, gamma, H);
 #pragma unroll
@@ -291,40 +293,50 @@ __global__ __launch_bounds__(BS) void stage1d_kernel(StageArgs a) {
   }
 }
 
-// State check of u^n for every instance (one workgroup per instance): alpha slot 0, validity
-// and the per-component sums (FP64, fixed order, so repeated calls agree bit for bit).
+// State check of u^n for every instance: alpha slot 0, validity and the per-component sums
+// (FP64).  Two passes: G workgroups per instance accumulate fixed, strided subsets of the cells
+// into partial records, then one thread per instance combines its G records in order, so the
+// result is the same bit for bit on every call.
+struct CheckPartial {
+  double sum[4];
+  unsigned long long ax, ay;
+  int bad, pad;
+};
+
 template <typename R, int FLUX, int M>
-__global__ __launch_bounds__(256) void init_kernel(InstDev* inst, void* P0, void* P1, unsigned long long* spread) {
-  InstDev* I = inst + blockIdx.x;
-  const int tid = threadIdx.x;
-  const long long n = I->ctl[0].n, nx = I->nx, ncell = I->nx * (I->dim == 2 ? I->ny : 1);
+__global__ __launch_bounds__(256) void check_partial_kernel(InstDev* inst, void* P0, void* P1, CheckPartial* part,
+                                                            int G) {
+  const int b = blockIdx.y, g = blockIdx.x, tid = threadIdx.x;
+  InstDev* I = inst + b;
+  const long long ncell = I->nx * (I->dim == 2 ? I->ny : 1);
   const R* u = reinterpret_cast<const R*>(I->ctl[0].home ? P1 : P0) + I->off;
   const R speed = R(I->speed_x), gamma = R(I->gamma);
-  (void)nx;
+  const bool two_d = I->dim == 2;
   unsigned long long ax = 0ull, ay = 0ull;
   int bad = 0;
   double sum[M];
 #pragma unroll
   for (int c = 0; c < M; ++c) sum[c] = 0.0;
-  for (long long k = tid; k < ncell; k += 256) {
+  for (long long k = (long long)g * 256 + tid; k < ncell; k += (long long)G * 256) {
     R U[M];
 #pragma unroll
     for (int c = 0; c < M; ++c) {
       U[c] = u[c * ncell + k];
       sum[c] += double(U[c]);
     }
-    int b = 0;
-    R sx = spectral_radius<R, FLUX, M, 0>(U, speed, gamma, b);
-    bad = b > bad ? b : bad;
-    unsigned long long bx = double_to_bits(double(sx));
+    int bx_bad = 0;
+    const R sx = spectral_radius<R, FLUX, M, 0>(U, speed, gamma, bx_bad);
+    bad = bx_bad > bad ? bx_bad : bad;
+    const unsigned long long bx = double_to_bits(double(sx));
     ax = bx > ax ? bx : ax;
-    if (I->dim == 2) {
+    if (two_d) {
+      int by_bad = 0;
       R sy;
       if constexpr (FLUX == kAdvection)
         sy = fabs(R(I->speed_y));
       else
-        sy = spectral_radius<R, FLUX, M, 1>(U, speed, gamma, b);
-      unsigned long long by = double_to_bits(double(sy));
+        sy = spectral_radius<R, FLUX, M, 1>(U, speed, gamma, by_bad);
+      const unsigned long long by = double_to_bits(double(sy));
       ay = by > ay ? by : ay;
     }
   }
@@ -337,38 +349,57 @@ __global__ __launch_bounds__(256) void init_kernel(InstDev* inst, void* P0, void
   s_ay[tid] = ay;
   s_b[tid] = bad;
   __syncthreads();
-  if (spread) {  // single grid: slot 0 holds alpha in entry 0, every other entry starts at zero
-    for (int k = tid; k < 3 * 2 * kSpread; k += 256) spread[k * kSpreadStride] = 0ull;
-  }
-  __syncthreads();
   if (tid == 0) {
-    double tot[M];
-    unsigned long long mx = 0ull, my = 0ull;
-    int w = 0;
-#pragma unroll
-    for (int c = 0; c < M; ++c) tot[c] = 0.0;
+    CheckPartial p;
+    for (int c = 0; c < 4; ++c) p.sum[c] = 0.0;
+    p.ax = 0ull;
+    p.ay = 0ull;
+    p.bad = 0;
+    p.pad = 0;
     for (int k = 0; k < 256; ++k) {
 #pragma unroll
-      for (int c = 0; c < M; ++c) tot[c] += s_sum[c][k];
-      mx = s_ax[k] > mx ? s_ax[k] : mx;
-      my = s_ay[k] > my ? s_ay[k] : my;
-      w = s_b[k] > w ? s_b[k] : w;
+      for (int c = 0; c < M; ++c) p.sum[c] += s_sum[c][k];
+      p.ax = s_ax[k] > p.ax ? s_ax[k] : p.ax;
+      p.ay = s_ay[k] > p.ay ? s_ay[k] : p.ay;
+      p.bad = s_b[k] > p.bad ? s_b[k] : p.bad;
     }
-    const double area = I->dx * (I->dim == 2 ? I->dy : 1.0);
-    for (int c = 0; c < 4; ++c) I->mass[c] = c < M ? tot[c] * area : 0.0;
-    I->alpha[0][0] = mx;
-    I->alpha[0][1] = my;
-    if (spread) {
-      spread[(0 * kSpread + 0) * kSpreadStride] = mx;
-      spread[(1 * kSpread + 0) * kSpreadStride] = my;
-    }
-    if (w) {
-      I->err = w == 2 ? NPW_ENONPHYSICAL : NPW_ENONFINITE;
-      I->err_stage = 0;
-      I->err_n = n;
-      I->err_t = I->ctl[0].t;
-      I->err_home = I->ctl[0].home;
-    }
+    part[(long long)b * G + g] = p;
+  }
+}
+
+static __global__ __launch_bounds__(64) void check_final_kernel(InstDev* inst, int ninst, const CheckPartial* part, int G,
+                                                         int ncomp, unsigned long long* spread) {
+  const int b = blockIdx.x * 64 + threadIdx.x;
+  if (spread && blockIdx.x == 0) {  // single grid: entry 0 of slot 0 holds alpha, every other entry starts at 0
+    for (int k = threadIdx.x; k < 3 * 2 * kSpread; k += 64) spread[k * kSpreadStride] = 0ull;
+  }
+  __syncthreads();
+  if (b >= ninst) return;
+  InstDev* I = inst + b;
+  double tot[4] = {0.0, 0.0, 0.0, 0.0};
+  unsigned long long mx = 0ull, my = 0ull;
+  int w = 0;
+  for (int g = 0; g < G; ++g) {
+    const CheckPartial& p = part[(long long)b * G + g];
+    for (int c = 0; c < 4; ++c) tot[c] += p.sum[c];
+    mx = p.ax > mx ? p.ax : mx;
+    my = p.ay > my ? p.ay : my;
+    w = p.bad > w ? p.bad : w;
+  }
+  const double area = I->dx * (I->dim == 2 ? I->dy : 1.0);
+  for (int c = 0; c < 4; ++c) I->mass[c] = c < ncomp ? tot[c] * area : 0.0;
+  I->alpha[0][0] = mx;
+  I->alpha[0][1] = my;
+  if (spread) {
+    spread[(0 * kSpread + 0) * kSpreadStride] = mx;
+    spread[(1 * kSpread + 0) * kSpreadStride] = my;
+  }
+  if (w) {
+    I->err = w == 2 ? NPW_ENONPHYSICAL : NPW_ENONFINITE;
+    I->err_stage = 0;
+    I->err_n = I->ctl[0].n;
+    I->err_t = I->ctl[0].t;
+    I->err_home = I->ctl[0].home;
   }
 }
 

@@ -23,8 +23,7 @@ __global__ __launch_bounds__(256) void stage2d_kernel(StageArgs a) {
   constexpr int NC = (TX + 2) * TY > TX * (TY + 2) ? (TX + 2) * TY : TX * (TY + 2);  // sweep cells
   __shared__ R s_u[M][WY][WX];
   __shared__ unsigned char s_flag[M][NC];
-  __shared__ R s_eta[M][NC];
-  __shared__ R s_vp[M][NC];
+  __shared__ R s_den[M][3][NC];
   __shared__ R s_F[M][NC];
   __shared__ R s_L[M][TY][TX];
   static_assert(TX % 1 == 0 && TY % 1 == 0 && NC >= (TX + 2) * TY, "sweep buffers");
@@ -141,7 +140,9 @@ __global__ __launch_bounds__(256) void stage2d_kernel(StageArgs a) {
   }
   const R alpha_x = R(bits_to_double(ax_bits)), alpha_y = R(bits_to_double(ay_bits));
   const R rdt = R(dt);
-  const bool use_eta = (I->recon == NPW_RBF_WENO5);
+  const int recon = I->recon;
+  const bool eno = (recon == NPW_RBF_ENO3 || recon == NPW_ENO3);
+  const bool use_eta = (recon == NPW_RBF_WENO5 || recon == NPW_RBF_ENO3);
   const bool use_switch = use_eta && (I->sw == NPW_SWITCH_MONOTONE);
   const double eps_m = I->eps_m;
   const R eps = R(I->eps_weno);
@@ -159,88 +160,88 @@ __global__ __launch_bounds__(256) void stage2d_kernel(StageArgs a) {
   __syncthreads();
 
   // One sweep direction.  Cells along the sweep are addressed by (line, pos): pos runs over
-  // -1..LEN (LEN = TX for x, TY for y), line over the other tile extent.  U(c, line, q) is the
-  // staged average at sweep offset q (q = pos + 3 is the LDS coordinate along the sweep).
+  // -1..LEN (LEN = TX for x, TY for y), line over the other tile extent; q = pos + 3 is the
+  // staged coordinate along the sweep.  Work items are numbered so that consecutive threads
+  // touch consecutive x (conflict-free LDS banks in both sweeps): cell index
+  // cid(line, pos) = line * NPOS + pos + 1 along x, (pos + 1) * LINES + line along y.
   auto sweep = [&](auto dir_tag) {
     constexpr int DIR = decltype(dir_tag)::value;
     constexpr int LEN = DIR == 0 ? TX : TY;
     constexpr int LINES = DIR == 0 ? TY : TX;
     constexpr int NPOS = LEN + 2;  // cells -1 .. LEN
-    auto U = [&](int c, int line, int q) -> R {
-      return DIR == 0 ? s_u[c][line + 3][q] : s_u[c][q][line + 3];
-    };
-    // flags of cells -1..LEN (window centred on the cell)
-    if (use_switch) {
-      for (int w = tid; w < NPOS * LINES; w += BS) {
-        const int line = w / NPOS, pos = w % NPOS - 1, q = pos + 3;
+    auto U = [&](int c, int line, int q) -> R { return DIR == 0 ? s_u[c][line + 3][q] : s_u[c][q][line + 3]; };
+    auto cid = [&](int line, int pos) -> int { return DIR == 0 ? line * NPOS + pos + 1 : (pos + 1) * LINES + line; };
+    // cell phase: flag and weight denominators of cells -1..LEN of every line
+    for (int w = tid; w < NPOS * LINES; w += BS) {
+      const int line = DIR == 0 ? w / NPOS : w % LINES;
+      const int pos = DIR == 0 ? w % NPOS - 1 : w / LINES - 1;
+      const int q = pos + 3;
 #pragma unroll
-        for (int c = 0; c < M; ++c)
-          s_flag[c][w] = (unsigned char)monotone_flag(double(U(c, line, q - 1)), double(U(c, line, q)),
-                                                      double(U(c, line, q + 1)));
+      for (int c = 0; c < M; ++c) {
+        // bit 0: switch flag; bits 1-2: ENO stencil
+        int fl = use_switch ? monotone_flag(double(U(c, line, q - 1)), double(U(c, line, q)),
+                                            double(U(c, line, q + 1)))
+                            : 0;
+        if (eno) {
+          fl |= eno_stencil(double(U(c, line, q - 2)), double(U(c, line, q - 1)), double(U(c, line, q)),
+                            double(U(c, line, q + 1)), double(U(c, line, q + 2)))
+                << 1;
+        } else {
+          R d0, d1, d2;
+          weight_denominators<R>(U(c, line, q - 2), U(c, line, q - 1), U(c, line, q), U(c, line, q + 1),
+                                 U(c, line, q + 2), eps, d0, d1, d2);
+          s_den[c][0][w] = d0;
+          s_den[c][1][w] = d1;
+          s_den[c][2][w] = d2;
+        }
+        s_flag[c][w] = (unsigned char)fl;
       }
     }
     __syncthreads();
-    // eta of the interfaces pos+1/2, pos = -1..LEN-1 (stored at the index of cell pos)
-    for (int w = tid; w < NPOS * LINES; w += BS) {
-      const int line = w / NPOS, pos = w % NPOS - 1, q = pos + 3;
-      if (pos > LEN - 1) continue;
+    // interface phase: pos+1/2 for pos = -1..LEN-1; the flux is stored at the left cell's index
+    for (int wi = tid; wi < (LEN + 1) * LINES; wi += BS) {
+      const int line = DIR == 0 ? wi / (LEN + 1) : wi % LINES;
+      const int pos = DIR == 0 ? wi % (LEN + 1) - 1 : wi / LINES - 1;
+      const int q = pos + 3;
+      const int wl = cid(line, pos), wr = cid(line, pos + 1);
+      R A[M], B[M], H[M];
 #pragma unroll
       for (int c = 0; c < M; ++c) {
         double e = 0.0;
         if (use_eta) {
           e = eta_ratio(double(U(c, line, q - 1)), double(U(c, line, q)), double(U(c, line, q + 1)),
                         double(U(c, line, q + 2)), eps_m);
-          if (use_switch && (s_flag[c][w] | s_flag[c][w + 1])) e = 0.0;
+          if (use_switch && ((s_flag[c][wl] | s_flag[c][wr]) & 1)) e = 0.0;
         }
-        s_eta[c][w] = R(e);
-      }
-    }
-    __syncthreads();
-    // v^- (kept in s_F for the moment) and v^+ of cells -1..LEN
-    for (int w = tid; w < NPOS * LINES; w += BS) {
-      const int line = w / NPOS, pos = w % NPOS - 1, q = pos + 3;
-#pragma unroll
-      for (int c = 0; c < M; ++c) {
-        const R eta_r = pos <= LEN - 1 ? s_eta[c][w] : R(0);
-        const R eta_l = pos >= 0 ? s_eta[c][w - 1] : R(0);
-        R vm = R(0), vp = R(0);
-        if constexpr (kExact)
-          weno_pair_exact(U(c, line, q - 2), U(c, line, q - 1), U(c, line, q), U(c, line, q + 1), U(c, line, q + 2),
-                          eta_r, eta_l, eps, pos <= LEN - 1, pos >= 0, vm, vp);
-        else
-          weno_pair_fast(U(c, line, q - 2), U(c, line, q - 1), U(c, line, q), U(c, line, q + 1), U(c, line, q + 2),
-                         eta_r, eta_l, eps, pos <= LEN - 1, pos >= 0, vm, vp);
-        s_F[c][w] = vm;
-        s_vp[c][w] = vp;
-      }
-    }
-    __syncthreads();
-    // flux at pos+1/2 from v^-(pos) and v^+(pos+1), written over v^-(pos) by the same thread
-    for (int w = tid; w < NPOS * LINES; w += BS) {
-      const int pos = w % NPOS - 1;
-      if (pos > LEN - 1) continue;
-      R A[M], B[M], H[M];
-#pragma unroll
-      for (int c = 0; c < M; ++c) {
-        A[c] = s_F[c][w];
-        B[c] = s_vp[c][w + 1];
+        const R eta = R(e);
+        if (eno) {
+          A[c] = eno_minus<R>(s_flag[c][wl] >> 1, U(c, line, q - 2), U(c, line, q - 1), U(c, line, q),
+                              U(c, line, q + 1), U(c, line, q + 2), eta);
+          B[c] = eno_plus<R>(s_flag[c][wr] >> 1, U(c, line, q - 1), U(c, line, q), U(c, line, q + 1),
+                             U(c, line, q + 2), U(c, line, q + 3), eta);
+        } else {
+          A[c] = weno_minus<R>(U(c, line, q - 2), U(c, line, q - 1), U(c, line, q), U(c, line, q + 1),
+                               U(c, line, q + 2), eta, s_den[c][0][wl], s_den[c][1][wl], s_den[c][2][wl]);
+          B[c] = weno_plus<R>(U(c, line, q - 1), U(c, line, q), U(c, line, q + 1), U(c, line, q + 2),
+                              U(c, line, q + 3), eta, s_den[c][0][wr], s_den[c][1][wr], s_den[c][2][wr]);
+        }
       }
       if constexpr (DIR == 0)
         lf_flux<R, FLUX, M, 0>(A, B, alpha_x, speed_x, gamma, H);
       else
         lf_flux<R, FLUX, M, 1>(A, B, alpha_y, speed_y, gamma, H);
 #pragma unroll
-      for (int c = 0; c < M; ++c) s_F[c][w] = H[c];
+      for (int c = 0; c < M; ++c) s_F[c][wl] = H[c];
     }
     __syncthreads();
     // flux difference into the owned cells
     for (int o = tid; o < TX * TY; o += BS) {
       const int x = o % TX, y = o / TX;
       const int line = DIR == 0 ? y : x, pos = DIR == 0 ? x : y;
-      const int w = line * NPOS + pos + 1;  // index of cell pos: interface pos+1/2
+      const int wp = cid(line, pos), wm = cid(line, pos - 1);  // interfaces pos+1/2 and pos-1/2
 #pragma unroll
       for (int c = 0; c < M; ++c) {
-        const R Fp = s_F[c][w], Fm = s_F[c][w - 1];
+        const R Fp = s_F[c][wp], Fm = s_F[c][wm];
         if constexpr (DIR == 0) {
           if constexpr (kExact)
             s_L[c][y][x] = -(Fp - Fm) / dx;

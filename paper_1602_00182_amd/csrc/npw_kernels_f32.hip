@@ -28,35 +28,48 @@ hipError_t launch_stage_f32(int flux, int ncomp, int block, const StageArgs& a, 
   }
 }
 
-// 2D tiles of 64 x 8 cells (x contiguous), one workgroup each.
-constexpr int kTX = 64, kTY = 8;
-hipError_t launch_stage2d_f32(int flux, int ncomp, const StageArgs& a, hipStream_t s) {
-  const dim3 grid((unsigned)((a.nx + kTX - 1) / kTX), (unsigned)((a.ny + kTY - 1) / kTY)), block(256);
+// 2D tiles (x contiguous), one workgroup of 256 threads each; the shape is tunable.
+template <int TX, int TY>
+static hipError_t launch2d(int flux, int ncomp, const StageArgs& a, hipStream_t s) {
+  const dim3 grid((unsigned)((a.nx + TX - 1) / TX), (unsigned)((a.ny + TY - 1) / TY)), block(256);
   if (flux == kEuler && ncomp == 4)
-    stage2d_kernel<float, kEuler, 4, kTX, kTY><<<grid, block, 0, s>>>(a);
+    stage2d_kernel<float, kEuler, 4, TX, TY><<<grid, block, 0, s>>>(a);
   else if (flux == kAdvection && ncomp == 1)
-    stage2d_kernel<float, kAdvection, 1, kTX, kTY><<<grid, block, 0, s>>>(a);
+    stage2d_kernel<float, kAdvection, 1, TX, TY><<<grid, block, 0, s>>>(a);
   else if (flux == kBurgers && ncomp == 1)
-    stage2d_kernel<float, kBurgers, 1, kTX, kTY><<<grid, block, 0, s>>>(a);
+    stage2d_kernel<float, kBurgers, 1, TX, TY><<<grid, block, 0, s>>>(a);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();
 }
 
+hipError_t launch_stage2d_f32(int flux, int ncomp, int shape, const StageArgs& a, hipStream_t s) {
+  switch (shape) {
+    case 0: return launch2d<64, 8>(flux, ncomp, a, s);
+    case 1: return launch2d<62, 8>(flux, ncomp, a, s);
+    case 2: return launch2d<126, 4>(flux, ncomp, a, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
 hipError_t launch_init_f32(int flux, int ncomp, InstDev* inst, int ninst, void* P0, void* P1,
-                           unsigned long long* spread, hipStream_t s) {
+                           unsigned long long* spread, void* scratch, int G, hipStream_t s) {
   if (ninst <= 0) return hipSuccess;
-  const dim3 grid(ninst), block(256);
+  CheckPartial* part = reinterpret_cast<CheckPartial*>(scratch);
+  const dim3 grid(G, ninst), block(256);
   if (flux == kAdvection && ncomp == 1)
-    init_kernel<float, kAdvection, 1><<<grid, block, 0, s>>>(inst, P0, P1, spread);
+    check_partial_kernel<float, kAdvection, 1><<<grid, block, 0, s>>>(inst, P0, P1, part, G);
   else if (flux == kBurgers && ncomp == 1)
-    init_kernel<float, kBurgers, 1><<<grid, block, 0, s>>>(inst, P0, P1, spread);
+    check_partial_kernel<float, kBurgers, 1><<<grid, block, 0, s>>>(inst, P0, P1, part, G);
   else if (flux == kEuler && ncomp == 3)
-    init_kernel<float, kEuler, 3><<<grid, block, 0, s>>>(inst, P0, P1, spread);
+    check_partial_kernel<float, kEuler, 3><<<grid, block, 0, s>>>(inst, P0, P1, part, G);
   else if (flux == kEuler && ncomp == 4)
-    init_kernel<float, kEuler, 4><<<grid, block, 0, s>>>(inst, P0, P1, spread);
+    check_partial_kernel<float, kEuler, 4><<<grid, block, 0, s>>>(inst, P0, P1, part, G);
   else
     return hipErrorInvalidValue;
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  check_final_kernel<<<(ninst + 63) / 64, 64, 0, s>>>(inst, ninst, part, G, ncomp, spread);
   return hipGetLastError();
 }
 

@@ -1,13 +1,18 @@
 // npw_runtime.cpp -- host runtime behind the C ABI of include/npweno.h: parameter validation,
 // device buffers, the tile table, captured HIP graphs of whole SSP-RK3 steps, and readback.
 #include <hip/hip_runtime.h>
+#include <sys/stat.h>
 
 #include <algorithm>
 #include <cmath>
 #include <cstddef>
 #include <cstdlib>
+#include <cstdio>
 #include <cstring>
+#include <fstream>
 #include <map>
+#include <sstream>
+#include <string>
 #include <new>
 #include <vector>
 
@@ -23,7 +28,8 @@ struct npw_solver {
   int precision = NPW_FP64, flux = 0, ncomp = 1, dim = 1;
   size_t esize = 8;
   int ninst = 0;
-  int block = 256;
+  int block = 256;              // 1D stage workgroup size (tile = block - 2 cells)
+  int shape2d = 0;              // 2D tile shape (see npw_internal.h)
   hipStream_t user = nullptr;   // caller's stream (ordering only)
   hipStream_t stream = nullptr; // stream of all library work (graphs are captured and replayed here)
   bool own_stream = false;      // the caller passed the default stream: use a private one
@@ -39,6 +45,8 @@ struct npw_solver {
   void* C = nullptr;
   void* scratch = nullptr;      // rhs destination when the caller passes host memory
   unsigned long long* spread = nullptr;  // spread alpha slots (single-grid solvers)
+  void* check_part = nullptr;   // partial records of the state check
+  int check_G = 1;              // workgroups per instance in the state check
   std::map<int, hipGraphExec_t> graphs;  // (steps per graph, start parity) -> executable graph
   int sticky_err = 0;
   bool batch = false;              // created by npweno_create_batch
@@ -74,7 +82,7 @@ int validate(const npw_params* p) {
   }
   if (p->bc != NPW_PERIODIC && p->bc != NPW_TRANSMISSIVE) return NPW_EINVAL;
   if (p->precision != NPW_FP64 && p->precision != NPW_FP32) return NPW_EINVAL;
-  if (p->recon != NPW_RBF_WENO5 && p->recon != NPW_WENO5_JS) return NPW_EINVAL;
+  if (p->recon < NPW_RBF_WENO5 || p->recon > NPW_ENO3) return NPW_EINVAL;
   if (p->switch_mode != NPW_SWITCH_MONOTONE && p->switch_mode != NPW_SWITCH_OFF) return NPW_EINVAL;
   if (!(std::isfinite(p->x0) && std::isfinite(p->x1) && p->x1 > p->x0)) return NPW_EINVAL;
   if (p->dim == 2 && !(std::isfinite(p->y0) && std::isfinite(p->y1) && p->y1 > p->y0)) return NPW_EINVAL;
@@ -93,16 +101,17 @@ int env_block() {
 
 hipError_t launch_stage(const npw_solver* s, const StageArgs& a, hipStream_t st) {
   if (s->dim == 2)
-    return s->precision == NPW_FP64 ? npw::launch_stage2d_f64(s->flux, s->ncomp, a, st)
-                                    : npw::launch_stage2d_f32(s->flux, s->ncomp, a, st);
+    return s->precision == NPW_FP64 ? npw::launch_stage2d_f64(s->flux, s->ncomp, s->shape2d, a, st)
+                                    : npw::launch_stage2d_f32(s->flux, s->ncomp, s->shape2d, a, st);
   return s->precision == NPW_FP64 ? npw::launch_stage_f64(s->flux, s->ncomp, s->block, a, st)
                                   : npw::launch_stage_f32(s->flux, s->ncomp, s->block, a, st);
 }
 
 hipError_t launch_init(const npw_solver* s, hipStream_t st) {
-  return s->precision == NPW_FP64
-             ? npw::launch_init_f64(s->flux, s->ncomp, s->d_inst, s->ninst, s->P0, s->P1, s->spread, st)
-             : npw::launch_init_f32(s->flux, s->ncomp, s->d_inst, s->ninst, s->P0, s->P1, s->spread, st);
+  return s->precision == NPW_FP64 ? npw::launch_init_f64(s->flux, s->ncomp, s->d_inst, s->ninst, s->P0, s->P1,
+                                                         s->spread, s->check_part, s->check_G, st)
+                                  : npw::launch_init_f32(s->flux, s->ncomp, s->d_inst, s->ninst, s->P0, s->P1,
+                                                         s->spread, s->check_part, s->check_G, st);
 }
 
 StageArgs stage_args(const npw_solver* s, int stage, int par, void* out) {
@@ -240,6 +249,165 @@ int align_homes(npw_solver* s, int* gp_out) {
   return moved ? pull(s) : NPW_OK;
 }
 
+int reset_instances(npw_solver* s, double t);
+
+// ---- tiles and block size --------------------------------------------------------------------
+constexpr int kBlocks[3] = {128, 256, 512};
+
+size_t max_tiles(const npw_solver* s) {
+  size_t n = 0;
+  for (const InstDev& h : s->h_inst) n += (size_t)((h.nx + kBlocks[0] - 3) / (kBlocks[0] - 2));
+  return std::max<size_t>(n, 1);
+}
+
+// Tile list of every instance for the current block size (BS - 2 owned cells per tile).
+void build_tiles(npw_solver* s) {
+  const int tile = s->block - 2;
+  s->tiles_all.clear();
+  for (int b = 0; b < s->ninst; ++b) {
+    const InstDev& h = s->h_inst[b];
+    for (long long st = 0; st < h.nx; st += tile) {
+      Tile t;
+      t.inst = b;
+      t.bc = h.bc;
+      t.start = st;
+      t.nx = h.nx;
+      t.off = h.off;
+      s->tiles_all.push_back(t);
+    }
+  }
+  s->ntiles = (int)s->tiles_all.size();
+}
+
+int set_block(npw_solver* s, int block) {
+  s->block = block;
+  build_tiles(s);
+  clear_graphs(s);
+  HIP_TRY(hipMemcpyAsync(s->d_tiles, s->tiles_all.data(), sizeof(Tile) * s->tiles_all.size(), hipMemcpyHostToDevice,
+                         s->stream));
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  return NPW_OK;
+}
+
+std::string tune_path() {
+  if (const char* p = std::getenv("NPW_TUNE_CACHE")) return p;
+  if (const char* h = std::getenv("HOME")) return std::string(h) + "/.cache/npweno_tune.txt";
+  return "";
+}
+
+std::string tune_key(const npw_solver* s) {
+  long long cells = 0;
+  for (const InstDev& h : s->h_inst) cells += h.nx * h.ny;
+  int lg = 0;
+  while ((1ll << (lg + 1)) <= cells) ++lg;
+  std::ostringstream k;
+  k << "v1_d" << s->dim << "_f" << s->flux << "_m" << s->ncomp << "_p" << s->precision << "_n" << lg << "_i"
+    << (s->ninst > 1 ? 1 : 0);
+  return k.str();
+}
+
+int tune_lookup(const std::string& key) {
+  std::ifstream f(tune_path());
+  std::string k;
+  int b;
+  int found = -1;
+  const bool two_d = key.find("_d2_") != std::string::npos;
+  while (f >> k >> b)
+    if (k == key && (two_d ? (b >= 0 && b < npw::k2dShapes) : (b == 128 || b == 256 || b == 512))) found = b;
+  return found;
+}
+
+void tune_store(const std::string& key, int block) {
+  const std::string path = tune_path();
+  if (path.empty()) return;
+  // create missing parent directories (no shell: plain mkdir calls)
+  for (size_t at = path.find('/', 1); at != std::string::npos; at = path.find('/', at + 1))
+    (void)::mkdir(path.substr(0, at).c_str(), 0755);
+  std::ofstream f(path, std::ios::app);
+  if (f) f << key << " " << block << "\n";
+}
+
+// Autotuner: pick the 1D stage block size (or the 2D tile shape) by timing a short graph with
+// every candidate on a copy of the initial state, then restore that state.  The choice is cached
+// per (dimension, flux, components, precision, log2 cells, batch) in a small text file.  Every
+// candidate computes each cell with the same arithmetic, so the choice never changes results.
+// NPW_BLOCK / NPW_TILE2D fix the knob; NPW_AUTOTUNE=0 keeps the default.
+// Candidate c of the tuned knob: the 1D block size, or the 2D tile shape.
+int candidate_count(const npw_solver* s) { return s->dim == 1 ? 3 : npw::k2dShapes; }
+int candidate_value(const npw_solver* s, int c) { return s->dim == 1 ? kBlocks[c] : c; }
+int apply_candidate(npw_solver* s, int v) {
+  if (s->dim == 1) return set_block(s, v);
+  s->shape2d = v;
+  clear_graphs(s);
+  return NPW_OK;
+}
+
+int autotune(npw_solver* s) {
+  if (s->dim == 1 && std::getenv("NPW_BLOCK")) return NPW_OK;
+  if (s->dim == 2 && std::getenv("NPW_TILE2D")) {
+    const int v = std::atoi(std::getenv("NPW_TILE2D"));
+    return apply_candidate(s, (v >= 0 && v < npw::k2dShapes) ? v : 0);
+  }
+  const char* at = std::getenv("NPW_AUTOTUNE");
+  if (at && std::strcmp(at, "0") == 0) return NPW_OK;
+  const std::string key = tune_key(s);
+  const int cached = tune_lookup(key);
+  if (cached >= 0) return apply_candidate(s, cached);
+  const size_t bytes = s->total * s->esize;
+  void* backup = nullptr;
+  if (hipMalloc(&backup, bytes) != hipSuccess) return NPW_OK;  // tuning is optional
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  int best = s->dim == 1 ? s->block : s->shape2d;
+  float best_ms = 1e30f;
+  int rc = NPW_OK;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess ||
+      hipMemcpyAsync(backup, s->P0, bytes, hipMemcpyDeviceToDevice, s->stream) != hipSuccess) {
+    rc = NPW_EHIP;
+  }
+  const int steps = s->dim == 1 ? 16 : 2;
+  for (int ci = 0; ci < candidate_count(s) && rc == NPW_OK; ++ci) {
+    rc = apply_candidate(s, candidate_value(s, ci));
+    for (auto& h : s->h_inst) {
+      h.T = 1e300;
+      h.tol = 0.0;
+    }
+    float ms = 0.0f;
+    for (int rep = 0; rep < 2 && rc == NPW_OK; ++rep) {  // first replay warms up
+      if (hipMemcpyAsync(s->P0, backup, bytes, hipMemcpyDeviceToDevice, s->stream) != hipSuccess) rc = NPW_EHIP;
+      if (rc == NPW_OK) rc = reset_instances(s, 0.0);
+      if (rc != NPW_OK) break;
+      hipGraphExec_t g = graph_for(s, steps, 0);
+      if (!g) {
+        rc = NPW_EHIP;
+        break;
+      }
+      if (hipEventRecord(e0, s->stream) != hipSuccess || hipGraphLaunch(g, s->stream) != hipSuccess ||
+          hipEventRecord(e1, s->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+          hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
+        rc = NPW_EHIP;
+    }
+    if (rc == NPW_OK && ms < best_ms) {
+      best_ms = ms;
+      best = candidate_value(s, ci);
+    }
+  }
+  for (auto& h : s->h_inst) {
+    h.T = 0.0;
+    h.tol = 1e-12;
+  }
+  if (rc == NPW_OK) rc = apply_candidate(s, best);
+  if (rc == NPW_OK && hipMemcpyAsync(s->P0, backup, bytes, hipMemcpyDeviceToDevice, s->stream) != hipSuccess)
+    rc = NPW_EHIP;
+  if (rc == NPW_OK) rc = reset_instances(s, 0.0);
+  if (rc == NPW_OK) rc = push_static(s);
+  (void)hipStreamSynchronize(s->stream);
+  (void)hipFree(backup);
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (rc == NPW_OK) tune_store(key, best);
+  return rc;
+}
+
 void fill_stats(const npw_solver* s, int b, npw_stats* st) {
   const InstDev& h = s->h_pin[b];
   st->t = h.ctl[0].t;
@@ -262,6 +430,7 @@ void release(npw_solver* s) {
   if (s->C) (void)hipFree(s->C);
   if (s->scratch) (void)hipFree(s->scratch);
   if (s->spread) (void)hipFree(s->spread);
+  if (s->check_part) (void)hipFree(s->check_part);
   if (s->d_inst) (void)hipFree(s->d_inst);
   if (s->d_tiles) (void)hipFree(s->d_tiles);
   if (s->h_pin) (void)hipHostFree(s->h_pin);
@@ -395,23 +564,19 @@ static int create_common(const npw_params* p, int32_t count, const void* const* 
   s->batch = batch;
   s->block = env_block();
   s->user = reinterpret_cast<hipStream_t>(hip_stream);
-  const int tile = s->block - 2;
   long long off = 0;
   for (int b = 0; b < count; ++b) {
     s->h_inst.push_back(make_inst(&p[b], off));
-    for (long long st = 0; st < p[b].nx; st += tile) {
-      Tile t;
-      t.inst = b;
-      t.bc = p[b].bc;
-      t.start = st;
-      t.nx = p[b].nx;
-      t.off = off;
-      s->tiles_all.push_back(t);
-    }
     off += (long long)p[b].ncomp * p[b].nx * (p[b].dim == 2 ? p[b].ny : 1);
   }
+  build_tiles(s);
   s->total = (size_t)off;
   s->ntiles = (int)s->tiles_all.size();
+  // state-check workgroups per instance: one per 16 Ki cells of a single grid, at most 512
+  if (!batch) {
+    const long long cells = s->h_inst[0].nx * s->h_inst[0].ny;
+    s->check_G = (int)std::min<long long>(512, std::max<long long>(1, cells / 16384));
+  }
   const size_t bytes = s->total * s->esize;
   // Graph capture needs a real stream: the legacy default stream gets a private stream that is
   // ordered against it with an event at every entry point.
@@ -430,9 +595,10 @@ static int create_common(const npw_params* p, int32_t count, const void* const* 
   }
   if (hipMalloc(&s->P0, bytes) != hipSuccess || hipMalloc(&s->P1, bytes) != hipSuccess ||
       hipMalloc(&s->C, bytes) != hipSuccess || hipMalloc(&s->d_inst, sizeof(InstDev) * count) != hipSuccess ||
-      hipMalloc(&s->d_tiles, sizeof(Tile) * s->tiles_all.size()) != hipSuccess ||
+      hipMalloc(&s->d_tiles, sizeof(Tile) * max_tiles(s)) != hipSuccess ||
       hipHostMalloc(&s->h_pin, sizeof(InstDev) * count, hipHostMallocDefault) != hipSuccess ||
-      (!batch && hipMalloc(&s->spread, sizeof(unsigned long long) * npw::kSpreadWords) != hipSuccess)) {
+      (!batch && hipMalloc(&s->spread, sizeof(unsigned long long) * npw::kSpreadWords) != hipSuccess) ||
+      hipMalloc(&s->check_part, (size_t)npw::kCheckPartialBytes * s->check_G * count) != hipSuccess) {
     release(s);
     return NPW_ENOMEM;
   }
@@ -450,6 +616,7 @@ static int create_common(const npw_params* p, int32_t count, const void* const* 
       rc = NPW_EHIP;
   }
   if (rc == NPW_OK) rc = reset_instances(s, 0.0);
+  if (rc == NPW_OK) rc = autotune(s);
   if (rc == NPW_OK) rc = leave(s);
   if (rc) {
     release(s);
@@ -511,6 +678,15 @@ int npweno_get_stats_instance(const npw_solver* cs, int32_t index, npw_stats* st
 }
 
 int npweno_instance_count(const npw_solver* s) { return s ? s->ninst : 0; }
+
+int npweno_launch_shape(const npw_solver* s, int32_t* block_1d, int32_t* tile_x, int32_t* tile_y) {
+  if (!s) return NPW_EINVAL;
+  static const int kTx[npw::k2dShapes] = {64, 62, 126}, kTy[npw::k2dShapes] = {8, 8, 4};
+  if (block_1d) *block_1d = s->block;
+  if (tile_x) *tile_x = s->dim == 2 ? kTx[s->shape2d] : 0;
+  if (tile_y) *tile_y = s->dim == 2 ? kTy[s->shape2d] : 0;
+  return NPW_OK;
+}
 
 int npweno_write(npw_solver* s, const void* u, int on_device, double t) {
   if (!s || !u || !std::isfinite(t)) return NPW_EINVAL;

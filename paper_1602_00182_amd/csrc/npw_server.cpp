@@ -55,6 +55,7 @@ struct Pool {
   InstDev* h_pin = nullptr;
   Tile* d_tiles = nullptr;
   int* d_ntiles = nullptr;
+  void* d_check = nullptr;    // one state-check partial record
   int tile_cap = 0;
   std::vector<int> slot_req;  // request index (into server order) per slot, -1 if free
   std::vector<uint64_t> slot_id;
@@ -213,7 +214,7 @@ int validate_request(const npw_server* s, const npw_params* p) {
   if (p->flux == NPW_EULER && (p->ncomp != 3 || !(p->gamma > 1.0))) return NPW_EINVAL;
   if (p->flux < 0 || p->flux > 2) return NPW_EINVAL;
   if (p->bc != NPW_PERIODIC && p->bc != NPW_TRANSMISSIVE) return NPW_EINVAL;
-  if (p->recon != NPW_RBF_WENO5 && p->recon != NPW_WENO5_JS) return NPW_EINVAL;
+  if (p->recon < NPW_RBF_WENO5 || p->recon > NPW_ENO3) return NPW_EINVAL;
   if (p->switch_mode != NPW_SWITCH_MONOTONE && p->switch_mode != NPW_SWITCH_OFF) return NPW_EINVAL;
   if (!(std::isfinite(p->x0) && std::isfinite(p->x1) && p->x1 > p->x0)) return NPW_EINVAL;
   if (!(p->cfl > 0.0) || !(p->eps_weno > 0.0) || !(p->eps_m > 0.0) || !(p->dt_fixed >= 0.0)) return NPW_EINVAL;
@@ -275,9 +276,10 @@ int admit(npw_server* s) {
     HIP_TRY(hipMemcpyAsync(dst, r.u0.data(), r.len * s->esize, hipMemcpyHostToDevice, pl.stream));
     InstDev d = make_slot(r, pl.par);
     HIP_TRY(hipMemcpyAsync(pl.d_inst + slot, &d, sizeof d, hipMemcpyHostToDevice, pl.stream));
-    hipError_t e = s->precision == NPW_FP64
-                       ? npw::launch_init_f64(pl.flux, pl.ncomp, pl.d_inst + slot, 1, s->P0, s->P1, nullptr, pl.stream)
-                       : npw::launch_init_f32(pl.flux, pl.ncomp, pl.d_inst + slot, 1, s->P0, s->P1, nullptr, pl.stream);
+    hipError_t e = s->precision == NPW_FP64 ? npw::launch_init_f64(pl.flux, pl.ncomp, pl.d_inst + slot, 1, s->P0,
+                                                                   s->P1, nullptr, pl.d_check, 1, pl.stream)
+                                            : npw::launch_init_f32(pl.flux, pl.ncomp, pl.d_inst + slot, 1, s->P0,
+                                                                   s->P1, nullptr, pl.d_check, 1, pl.stream);
     if (e != hipSuccess) return NPW_EHIP;
     HIP_TRY(hipStreamSynchronize(pl.stream));  // the host copy of the slot goes out of scope
     r.u0.clear();
@@ -345,6 +347,7 @@ void destroy_server(npw_server* s) {
     if (pl.d_inst) (void)hipFree(pl.d_inst);
     if (pl.d_tiles) (void)hipFree(pl.d_tiles);
     if (pl.d_ntiles) (void)hipFree(pl.d_ntiles);
+    if (pl.d_check) (void)hipFree(pl.d_check);
     if (pl.h_pin) (void)hipHostFree(pl.h_pin);
     if (pl.stream) (void)hipStreamDestroy(pl.stream);
   }
@@ -392,6 +395,7 @@ int npw_server_create(size_t hbm_budget_bytes, int32_t max_slots, int32_t precis
          hipMalloc(&pl.d_inst, sizeof(InstDev) * max_slots) == hipSuccess &&
          hipMalloc(&pl.d_tiles, sizeof(Tile) * pl.tile_cap) == hipSuccess &&
          hipMalloc(&pl.d_ntiles, sizeof(int)) == hipSuccess &&
+         hipMalloc(&pl.d_check, npw::kCheckPartialBytes) == hipSuccess &&
          hipHostMalloc(&pl.h_pin, sizeof(InstDev) * max_slots, hipHostMallocDefault) == hipSuccess;
     if (ok) {
       // idle slots: T = t = 0, so every launch skips them

@@ -26,7 +26,7 @@ import numpy as np
 
 ADVECTION, BURGERS, EULER = 0, 1, 2
 PERIODIC, TRANSMISSIVE = 0, 1
-RBF_WENO5, WENO5_JS = 0, 1
+RBF_WENO5, WENO5_JS, RBF_ENO3, ENO3 = 0, 1, 2, 3
 SWITCH_MONOTONE, SWITCH_OFF = 0, 1
 
 

@@ -360,5 +360,10 @@ def test_eno_euler_and_burgers(prec):
         uo, _, _ = O.solve(_oracle_problem(w), u0.astype(np.float64), w.T, max_steps=80)
         if prec == B.FP64:
             assert np.array_equal(u, uo)
-        else:
+        elif w.flux == I.BURGERS:  # smooth data (80 steps end long before the shock forms)
             assert np.mean(np.abs(u - uo)) <= 1e-5
+        else:
+            # Sod: the ENO stencil choice is a discontinuous function of the data, and FP32
+            # rounding may tip a tie-like comparison next to the jumps, moving a few cells by a
+            # fraction of the jump (<= 0.9 here); 2e-4 mean allows about one such cell in 500.
+            assert np.mean(np.abs(u - uo)) <= 2e-4
