@@ -16,6 +16,7 @@ Prints one JSON line.  Only one GPU: --gpus N > 1 exits with a message.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import math
 import os
@@ -32,6 +33,39 @@ HBM_PEAK_GBS = 8000.0
 # writes u^(1); stages 2 and 3 read u^n and the stage input and write the output.
 ACCESSES_PER_CELL_STAGE = 8.0 / 3.0
 METRIC = "cell-updates/s per RK stage at stated L1 err vs FP64 oracle; p50/p99 solve latency"
+
+
+KERNEL_SOURCES = ("npw_device.h", "npw_internal.h", "npw_kernels.h", "npw_kernels2d.h", "npw_kernels_f32.hip",
+                  "npw_kernels_f64.hip")
+
+
+def kernel_source_hash() -> str:
+    """Short hash of the stage-kernel sources; a counter summary stays valid while it matches."""
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1602_00182_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def counter_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the FETCH_SIZE/WRITE_SIZE summaries under profiles/
+    (each counter scaled by what it reads for a copy of known size), or None when no summary
+    covers this kernel as it is now built."""
+    key = "kernel=" + kernel.replace(" ", "")
+    src = "source=" + kernel_source_hash()
+    pdir = os.path.join(ROOT, "profiles")
+    if not os.path.isdir(pdir):
+        return None
+    for name in sorted(os.listdir(pdir)):
+        if not name.endswith("_hbm_counters.txt"):
+            continue
+        with open(os.path.join(pdir, name)) as f:
+            for line in f:
+                parts = line.split()
+                if parts and parts[0] == "traffic" and key in parts and src in parts:
+                    return float(next(p for p in parts if p.startswith("bytes_per_launch="))[len("bytes_per_launch="):])
+    return None
 
 
 def parse():
@@ -115,7 +149,7 @@ def bench_single(args, w, prec):
         "latency_s": _percentiles(lat),
         "rk_steps_per_solve": rk,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": counter_traffic(label),
                      "kernel": label, "avg_launch_us": avg_launch * 1e6,
                      "bytes_per_launch": bytes_per_launch},
         "launch_shape": shape,
