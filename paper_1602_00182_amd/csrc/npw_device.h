@@ -8,6 +8,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include "../../include/npweno.h"
 #include "npw_internal.h"
 
 namespace npw {
@@ -204,6 +205,101 @@ __device__ __forceinline__ R weno_plus(R a, R b, R c, R d, R e, R eta, R s0, R s
     return weno_plus_exact(a, b, c, d, e, eta, s0, s1, s2);
   else
     return weno_plus_fast(a, b, c, d, e, eta, s0, s1, s2);
+}
+
+// What a reconstruction code asks of the kernels.
+struct ReconMode {
+  bool k2;          // k = 2 (Table 2) instead of k = 3 (Table 3)
+  bool eno;         // one stencil per cell (ENO) instead of the weighted combination
+  bool use_eta;     // the multiquadric perturbation is on
+  bool use_switch;  // the Section 4 switch zeroes it near non-monotone windows
+};
+__device__ __forceinline__ ReconMode recon_mode(int recon, int sw) {
+  ReconMode m;
+  m.k2 = recon >= NPW_RBF_WENO3;
+  m.eno = recon == NPW_RBF_ENO3 || recon == NPW_ENO3 || recon == NPW_RBF_ENO2 || recon == NPW_ENO2;
+  m.use_eta = recon == NPW_RBF_WENO5 || recon == NPW_RBF_ENO3 || recon == NPW_RBF_WENO3 || recon == NPW_RBF_ENO2;
+  m.use_switch = m.use_eta && sw == NPW_SWITCH_MONOTONE;
+  return m;
+}
+
+// ---- k = 2 (Sections 3.1-3.2, Table 2) -------------------------------------------------------
+// Row r (-1, 0, 1) of Table 2 at x_{i+1/2} applied to (w0, w1) = (u_{i-r}, u_{i-r+1}): polynomial
+// part plus eta times the multiquadric perturbation.
+template <typename R, int ROW>
+__device__ __forceinline__ R table2_row(R w0, R w1, R eta) {
+  if constexpr (ROW == -1)
+    return (R(3.0 / 2.0) + eta * R(-3.0 / 2.0)) * w0 + (R(-1.0 / 2.0) + eta * R(1.0 / 2.0)) * w1;
+  else if constexpr (ROW == 0)
+    return (R(1.0 / 2.0) + eta * R(1.0 / 4.0)) * w0 + (R(1.0 / 2.0) + eta * R(1.0 / 4.0)) * w1;
+  else
+    return (R(-1.0 / 2.0) + eta * R(1.0 / 2.0)) * w0 + (R(3.0 / 2.0) + eta * R(-3.0 / 2.0)) * w1;
+}
+
+// Shape parameter of a cell for one edge (Table 2 caption): twice the second undivided
+// difference over the three-point estimate -u_far + 5 u_0 + 2 u_near of six times the edge
+// value, eps_M added with the sign of the denominator.  For the right edge of cell i pass
+// (u_{i-1}, u_i, u_{i+1}); for its left edge the mirror (u_{i+1}, u_i, u_{i-1}).  Double,
+// uncontracted.
+__device__ __forceinline__ double eta2_ratio(double ufar, double u0, double unear, double eps_m) {
+#pragma clang fp contract(off)
+  double num = 2.0 * (-ufar + 2.0 * u0 - unear);
+  double den = -ufar + 5.0 * u0 + 2.0 * unear;
+  if (den >= 0.0)
+    den = den + eps_m;
+  else
+    den = den - eps_m;
+  return num / den;
+}
+
+// WENO3 edge values of cell i from (a, b, c) = u_{i-1}, u_i, u_{i+1}: v^-_{i+1/2} combines row 0 on
+// {i, i+1} and row 1 on {i-1, i} with linear weights 2/3, 1/3; v^+_{i-1/2} combines row -1 on
+// {i, i+1} and row 0 on {i-1, i} with 1/3, 2/3.  beta_0 = (u_{i+1} - u_i)^2, beta_1 = (u_i - u_{i-1})^2,
+// alpha_r = d_r / (eps + beta_r)^2.  Exact flavour in the order of that definition.
+template <bool PLUS>
+__device__ __forceinline__ double weno3_exact(double a, double b, double c, double eta, double eps) {
+#pragma clang fp contract(off)
+  double t = c - b;
+  const double b0 = t * t;
+  t = b - a;
+  const double b1 = t * t;
+  const double d0 = PLUS ? 1.0 / 3.0 : 2.0 / 3.0, d1 = PLUS ? 2.0 / 3.0 : 1.0 / 3.0;
+  const double a0 = d0 / ((eps + b0) * (eps + b0));
+  const double a1 = d1 / ((eps + b1) * (eps + b1));
+  const double s = a0 + a1;
+  const double w0 = a0 / s, w1 = a1 / s;
+  if (PLUS)
+    return w0 * table2_row<double, -1>(b, c, eta) + w1 * table2_row<double, 0>(a, b, eta);
+  return w0 * table2_row<double, 0>(b, c, eta) + w1 * table2_row<double, 1>(a, b, eta);
+}
+template <bool PLUS>
+__device__ __forceinline__ float weno3_fast(float a, float b, float c, float eta, float eps) {
+  const float g0 = eps + (c - b) * (c - b), g1 = eps + (b - a) * (b - a);
+  const float a0 = (PLUS ? 1.0f / 3.0f : 2.0f / 3.0f) * __builtin_amdgcn_rcpf(g0 * g0);
+  const float a1 = (PLUS ? 2.0f / 3.0f : 1.0f / 3.0f) * __builtin_amdgcn_rcpf(g1 * g1);
+  const float q0 = PLUS ? table2_row<float, -1>(b, c, eta) : table2_row<float, 0>(b, c, eta);
+  const float q1 = PLUS ? table2_row<float, 0>(a, b, eta) : table2_row<float, 1>(a, b, eta);
+  return (a0 * q0 + a1 * q1) * __builtin_amdgcn_rcpf(a0 + a1);
+}
+template <typename R, bool PLUS>
+__device__ __forceinline__ R weno3(R a, R b, R c, R eta, R eps) {
+  if constexpr (sizeof(R) == 8)
+    return weno3_exact<PLUS>(a, b, c, eta, eps);
+  else
+    return weno3_fast<PLUS>(a, b, c, eta, eps);
+}
+
+// ENO stencil of cell i for k = 2 from (u_{i-1}, u_i, u_{i+1}): 1 ({i-1, i}) when its undivided
+// difference is strictly smaller, else 0 ({i, i+1}).  Double.
+__device__ __forceinline__ int eno2_stencil(double a, double b, double c) {
+#pragma clang fp contract(off)
+  return fabs(b - a) < fabs(c - b) ? 1 : 0;
+}
+// ENO2 edge values of cell i with stencil r: v^- uses row r, v^+ row r - 1, on {i-r, i-r+1}.
+template <typename R, bool PLUS>
+__device__ __forceinline__ R eno2(int r, R a, R b, R c, R eta) {
+  if (r == 0) return PLUS ? table2_row<R, -1>(b, c, eta) : table2_row<R, 0>(b, c, eta);
+  return PLUS ? table2_row<R, 0>(a, b, eta) : table2_row<R, 1>(a, b, eta);
 }
 
 // Physical flux along direction DIR (0: x, 1: y) of the state U[0..M-1] (Section 5.1; Euler as in

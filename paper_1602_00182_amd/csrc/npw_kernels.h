@@ -134,10 +134,8 @@ __device__ __forceinline__ void stage1d_tile(const StageArgs& a, const Tile tile
   }
   const R alpha = R(bits_to_double(alpha_bits));
   const R rdt = R(dt);
-  const int recon = I->recon;
-  const bool eno = (recon == NPW_RBF_ENO3 || recon == NPW_ENO3);
-  const bool use_eta = (recon == NPW_RBF_WENO5 || recon == NPW_RBF_ENO3);
-  const bool use_switch = use_eta && (I->sw == NPW_SWITCH_MONOTONE);
+  const ReconMode rm = recon_mode(I->recon, I->sw);
+  const bool k2 = rm.k2, eno = rm.eno, use_eta = rm.use_eta, use_switch = rm.use_switch;
   const double eps_m = I->eps_m;
   const R eps = R(I->eps_weno);
   const R speed = R(I->speed_x), gamma = R(I->gamma);
@@ -172,7 +170,18 @@ __device__ __forceinline__ void stage1d_tile(const StageArgs& a, const Tile tile
   for (int c = 0; c < M; ++c) {
     // bit 0: switch flag; bits 1-2: ENO stencil
     int fl = use_switch ? monotone_flag(D(c, tid + 1), D(c, tid + 2), D(c, tid + 3)) : 0;
-    if (eno) {
+    if (k2) {
+      // k = 2: the cell's ENO2 stencil, and its right- and left-edge shape parameters (zero
+      // when the cell's window is flagged), kept in the denominator slots 0 and 1
+      if (eno) fl |= eno2_stencil(D(c, tid + 1), D(c, tid + 2), D(c, tid + 3)) << 1;
+      double er = 0.0, el = 0.0;
+      if (use_eta && !(fl & 1)) {
+        er = eta2_ratio(D(c, tid + 1), D(c, tid + 2), D(c, tid + 3), eps_m);
+        el = eta2_ratio(D(c, tid + 3), D(c, tid + 2), D(c, tid + 1), eps_m);
+      }
+      s_den[c][0][tid] = R(er);
+      s_den[c][1][tid] = R(el);
+    } else if (eno) {
       fl |= eno_stencil(D(c, tid), D(c, tid + 1), D(c, tid + 2), D(c, tid + 3), D(c, tid + 4)) << 1;
     } else {
       R d0, d1, d2;
@@ -192,6 +201,17 @@ __device__ __forceinline__ void stage1d_tile(const StageArgs& a, const Tile tile
     R A[M], B[M], H[M];
 #pragma unroll
     for (int c = 0; c < M; ++c) {
+      if (k2) {  // left cell LDS tid+2, right cell tid+3; each edge with its own cell's eta
+        const R el = s_den[c][0][tid], er = s_den[c][1][tid + 1];
+        if (eno) {
+          A[c] = eno2<R, false>((s_flag[c][tid] >> 1) & 1, s_u[c][tid + 1], s_u[c][tid + 2], s_u[c][tid + 3], el);
+          B[c] = eno2<R, true>((s_flag[c][tid + 1] >> 1) & 1, s_u[c][tid + 2], s_u[c][tid + 3], s_u[c][tid + 4], er);
+        } else {
+          A[c] = weno3<R, false>(s_u[c][tid + 1], s_u[c][tid + 2], s_u[c][tid + 3], el, eps);
+          B[c] = weno3<R, true>(s_u[c][tid + 2], s_u[c][tid + 3], s_u[c][tid + 4], er, eps);
+        }
+        continue;
+      }
       double e = 0.0;
       if (use_eta) {
         e = eta_ratio(D(c, tid + 1), D(c, tid + 2), D(c, tid + 3), D(c, tid + 4), eps_m);

@@ -140,10 +140,8 @@ __global__ __launch_bounds__(256) void stage2d_kernel(StageArgs a) {
   }
   const R alpha_x = R(bits_to_double(ax_bits)), alpha_y = R(bits_to_double(ay_bits));
   const R rdt = R(dt);
-  const int recon = I->recon;
-  const bool eno = (recon == NPW_RBF_ENO3 || recon == NPW_ENO3);
-  const bool use_eta = (recon == NPW_RBF_WENO5 || recon == NPW_RBF_ENO3);
-  const bool use_switch = use_eta && (I->sw == NPW_SWITCH_MONOTONE);
+  const ReconMode rm = recon_mode(I->recon, I->sw);
+  const bool k2 = rm.k2, eno = rm.eno, use_eta = rm.use_eta, use_switch = rm.use_switch;
   const double eps_m = I->eps_m;
   const R eps = R(I->eps_weno);
   const R speed_x = R(I->speed_x), speed_y = R(I->speed_y), gamma = R(I->gamma);
@@ -182,7 +180,17 @@ __global__ __launch_bounds__(256) void stage2d_kernel(StageArgs a) {
         int fl = use_switch ? monotone_flag(double(U(c, line, q - 1)), double(U(c, line, q)),
                                             double(U(c, line, q + 1)))
                             : 0;
-        if (eno) {
+        if (k2) {  // k = 2: ENO2 stencil and the right/left edge shape parameters of the cell
+          const double um = double(U(c, line, q - 1)), u0 = double(U(c, line, q)), up = double(U(c, line, q + 1));
+          if (eno) fl |= eno2_stencil(um, u0, up) << 1;
+          double er = 0.0, el = 0.0;
+          if (use_eta && !(fl & 1)) {
+            er = eta2_ratio(um, u0, up, eps_m);
+            el = eta2_ratio(up, u0, um, eps_m);
+          }
+          s_den[c][0][w] = R(er);
+          s_den[c][1][w] = R(el);
+        } else if (eno) {
           fl |= eno_stencil(double(U(c, line, q - 2)), double(U(c, line, q - 1)), double(U(c, line, q)),
                             double(U(c, line, q + 1)), double(U(c, line, q + 2)))
                 << 1;
@@ -207,6 +215,17 @@ __global__ __launch_bounds__(256) void stage2d_kernel(StageArgs a) {
       R A[M], B[M], H[M];
 #pragma unroll
       for (int c = 0; c < M; ++c) {
+        if (k2) {
+          const R el = s_den[c][0][wl], er = s_den[c][1][wr];
+          if (eno) {
+            A[c] = eno2<R, false>((s_flag[c][wl] >> 1) & 1, U(c, line, q - 1), U(c, line, q), U(c, line, q + 1), el);
+            B[c] = eno2<R, true>((s_flag[c][wr] >> 1) & 1, U(c, line, q), U(c, line, q + 1), U(c, line, q + 2), er);
+          } else {
+            A[c] = weno3<R, false>(U(c, line, q - 1), U(c, line, q), U(c, line, q + 1), el, eps);
+            B[c] = weno3<R, true>(U(c, line, q), U(c, line, q + 1), U(c, line, q + 2), er, eps);
+          }
+          continue;
+        }
         double e = 0.0;
         if (use_eta) {
           e = eta_ratio(double(U(c, line, q - 1)), double(U(c, line, q)), double(U(c, line, q + 1)),

@@ -214,7 +214,7 @@ int validate_request(const npw_server* s, const npw_params* p) {
   if (p->flux == NPW_EULER && (p->ncomp != 3 || !(p->gamma > 1.0))) return NPW_EINVAL;
   if (p->flux < 0 || p->flux > 2) return NPW_EINVAL;
   if (p->bc != NPW_PERIODIC && p->bc != NPW_TRANSMISSIVE) return NPW_EINVAL;
-  if (p->recon < NPW_RBF_WENO5 || p->recon > NPW_ENO3) return NPW_EINVAL;
+  if (p->recon < NPW_RBF_WENO5 || p->recon > NPW_ENO2) return NPW_EINVAL;
   if (p->switch_mode != NPW_SWITCH_MONOTONE && p->switch_mode != NPW_SWITCH_OFF) return NPW_EINVAL;
   if (!(std::isfinite(p->x0) && std::isfinite(p->x1) && p->x1 > p->x0)) return NPW_EINVAL;
   if (!(p->cfl > 0.0) || !(p->eps_weno > 0.0) || !(p->eps_m > 0.0) || !(p->dt_fixed >= 0.0)) return NPW_EINVAL;

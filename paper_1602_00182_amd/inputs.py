@@ -26,7 +26,8 @@ import numpy as np
 
 ADVECTION, BURGERS, EULER = 0, 1, 2
 PERIODIC, TRANSMISSIVE = 0, 1
-RBF_WENO5, WENO5_JS, RBF_ENO3, ENO3 = 0, 1, 2, 3
+RBF_WENO5, WENO5_JS, RBF_ENO3, ENO3 = 0, 1, 2, 3  # k = 3 (Table 3)
+RBF_WENO3, WENO3_JS, RBF_ENO2, ENO2 = 4, 5, 6, 7  # k = 2 (Table 2)
 SWITCH_MONOTONE, SWITCH_OFF = 0, 1
 
 
