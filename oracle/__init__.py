@@ -47,6 +47,7 @@ class _Problem(ctypes.Structure):
         ("speed_x", ctypes.c_double), ("speed_y", ctypes.c_double), ("gamma", ctypes.c_double),
         ("cfl", ctypes.c_double), ("eps_weno", ctypes.c_double), ("eps_m", ctypes.c_double),
         ("recon", ctypes.c_int), ("switch_mode", ctypes.c_int), ("dt_fixed", ctypes.c_double),
+        ("charwise", ctypes.c_int),
     ]
 
 
@@ -72,11 +73,13 @@ class Problem:
     recon: int = RBF_WENO5
     switch_mode: int = SWITCH_MONOTONE
     dt_fixed: float = 0.0
+    charwise: int = 0
 
     def c(self) -> _Problem:
         return _Problem(self.dim, self.flux, self.ncomp, self.bc, self.nx, self.ny if self.dim == 2 else 1,
                         self.x0, self.x1, self.y0, self.y1, self.speed_x, self.speed_y, self.gamma,
-                        self.cfl, self.eps_weno, self.eps_m, self.recon, self.switch_mode, self.dt_fixed)
+                        self.cfl, self.eps_weno, self.eps_m, self.recon, self.switch_mode, self.dt_fixed,
+                        self.charwise)
 
     @property
     def ncell(self) -> int:
@@ -122,6 +125,7 @@ def lib():
         L.npo_eta2.argtypes = [ctypes.c_double] * 4
         L.npo_eta2.restype = ctypes.c_double
         L.npo_line_states.argtypes = [P, _D, ctypes.c_long, _D, _D, _D, _I]
+        L.npo_char_basis.argtypes = [P, ctypes.c_int, _D, _D, _D, _D, _D]
         L.npo_alpha.argtypes = [P, _D, _D]
         L.npo_alpha.restype = ctypes.c_int
         L.npo_rhs.argtypes = [P, _D, _D, _D]
@@ -215,6 +219,19 @@ class OracleError(RuntimeError):
     def __init__(self, rc):
         super().__init__(f"oracle returned {rc}")
         self.rc = rc
+
+
+def char_basis(pb: Problem, direction: int, UL, UR):
+    """(Lm, Rm, lam) of the Euler flux Jacobian along `direction` at the Roe average of UL, UR:
+    rows of Lm are left eigenvectors, columns of Rm right eigenvectors."""
+    m = pb.ncomp
+    UL, UR = _f64(UL).copy(), _f64(UR).copy()
+    Lm, Rm, lam = np.zeros(m * m), np.zeros(m * m), np.zeros(m)
+    p = pb.c()
+    rc = lib().npo_char_basis(ctypes.byref(p), direction, _dp(UL), _dp(UR), _dp(Lm), _dp(Rm), _dp(lam))
+    if rc:
+        raise OracleError(rc)
+    return Lm.reshape(m, m), Rm.reshape(m, m), lam
 
 
 def alpha(pb: Problem, u):

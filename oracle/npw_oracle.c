@@ -353,78 +353,196 @@ static long ghost(long i, long n, int bc) {
 /* ------------------------------------------------------------------------------------ */
 static int is_k2(int recon) { return recon >= NPO_RBF_WENO3; }
 
-/* k = 2 interface states: cell i gives v^-_{i+1/2} with its right-edge eta and cell i+1 gives
- * v^+_{i+1/2} with its left-edge eta; the Section 4 switch (stated for k = 2) zeroes both etas of
- * a cell whose window {i-1, i, i+1} is not monotone. */
-static void line_states_k2(const npo_problem* pb, const double* line, long n, double* vminus, double* vplus,
-                           double* eta_out, int* flag_out) {
-#define G(k) line[ghost((k), n, pb->bc)]
-  const int rbf = pb->recon == NPO_RBF_WENO3 || pb->recon == NPO_RBF_ENO2;
-  const int weno = pb->recon == NPO_RBF_WENO3 || pb->recon == NPO_WENO3_JS;
-  for (long i = -1; i <= n - 1; ++i) {
-    double uL[3] = {G(i - 1), G(i), G(i + 1)};     /* cell i */
-    double uR[3] = {G(i), G(i + 1), G(i + 2)};     /* cell i+1 */
+/* States at one interface x_{i+1/2} from the six-cell window w = (u_{i-2}, .., u_{i+3}) of one
+ * scalar field: v^- of cell i, v^+ of cell i+1, the shape parameter used and the switch flag.
+ *
+ * k = 3 (Table 3): one eta per interface from u_{i-1}..u_{i+2} (Table 3 caption).  Reading (k = 3
+ * switch): the interface's eta vanishes when either three-cell window centred on a cell adjacent to
+ * it fails the Section 4 monotone test.  v^- uses cells i-2..i+2, v^+ cells i-1..i+3.
+ *
+ * k = 2 (Table 2): cell i gives v^-_{i+1/2} with its right-edge eta and cell i+1 gives v^+_{i+1/2}
+ * with its left-edge eta (Section 3.2 estimate); the Section 4 switch (stated for k = 2) zeroes
+ * both etas of a cell whose window {i-1, i, i+1} is not monotone.  The eta reported is cell i's. */
+static void interface_states(const npo_problem* pb, const double w[6], double* vm, double* vp, double* eta_out,
+                             int* flag_out) {
+  double eta = 0.0;
+  int flag = 0;
+  if (is_k2(pb->recon)) {
+    const double* uL = w + 1; /* cell i:   u_{i-1}, u_i, u_{i+1} */
+    const double* uR = w + 2; /* cell i+1: u_i, u_{i+1}, u_{i+2} */
+    const int rbf = pb->recon == NPO_RBF_WENO3 || pb->recon == NPO_RBF_ENO2;
     double eL = 0.0, eR = 0.0;
-    int flag = 0;
     if (rbf) {
-      eL = npo_eta2(uL[0], uL[1], uL[2], pb->eps_m);  /* right edge of cell i */
-      eR = npo_eta2(uR[2], uR[1], uR[0], pb->eps_m);  /* left edge of cell i+1 (mirror) */
+      eL = npo_eta2(uL[0], uL[1], uL[2], pb->eps_m); /* right edge of cell i */
+      eR = npo_eta2(uR[2], uR[1], uR[0], pb->eps_m); /* left edge of cell i+1 (mirror) */
       if (pb->switch_mode == NPO_SWITCH_MONOTONE) {
         if (npo_monotone_flag(uL[0], uL[1], uL[2])) eL = 0.0, flag = 1;
         if (npo_monotone_flag(uR[0], uR[1], uR[2])) eR = 0.0, flag = 1;
       }
     }
-    if (weno) {
-      vminus[i + 1] = npo_weno3_minus(uL, eL, pb->eps_weno);
-      vplus[i + 1] = npo_weno3_plus(uR, eR, pb->eps_weno);
+    if (pb->recon == NPO_RBF_WENO3 || pb->recon == NPO_WENO3_JS) {
+      *vm = npo_weno3_minus(uL, eL, pb->eps_weno);
+      *vp = npo_weno3_plus(uR, eR, pb->eps_weno);
     } else {
-      vminus[i + 1] = npo_eno2_minus(uL, eL);
-      vplus[i + 1] = npo_eno2_plus(uR, eR);
+      *vm = npo_eno2_minus(uL, eL);
+      *vp = npo_eno2_plus(uR, eR);
     }
-    if (eta_out) eta_out[i + 1] = eL;
-    if (flag_out) flag_out[i + 1] = flag;
-  }
-#undef G
-}
-
-void npo_line_states(const npo_problem* pb, const double* line, long n, double* vminus,
-                     double* vplus, double* eta_out, int* flag_out) {
-  if (is_k2(pb->recon)) {
-    line_states_k2(pb, line, n, vminus, vplus, eta_out, flag_out);
-    return;
-  }
-  /* G(k) = cell average of cell k (ghosts included), k = -3..n+2 */
-#define G(k) line[ghost((k), n, pb->bc)]
-  for (long i = -1; i <= n - 1; ++i) {
-    /* interface x_{i+1/2}, stored at index i+1 */
-    double eta = 0.0;
-    int flag = 0;
+    eta = eL;
+  } else {
     if (pb->recon == NPO_RBF_WENO5 || pb->recon == NPO_RBF_ENO3) {
-      eta = npo_eta(G(i - 1), G(i), G(i + 1), G(i + 2), pb->eps_m);
+      eta = npo_eta(w[1], w[2], w[3], w[4], pb->eps_m);
       if (pb->switch_mode == NPO_SWITCH_MONOTONE) {
-        /* Reading (k = 3 switch): the interface's eta vanishes when either 3-cell window
-         * centred on a cell adjacent to it is not monotone, each window tested with the
-         * Section 4 criterion. */
-        flag = npo_monotone_flag(G(i - 1), G(i), G(i + 1)) || npo_monotone_flag(G(i), G(i + 1), G(i + 2));
+        flag = npo_monotone_flag(w[1], w[2], w[3]) || npo_monotone_flag(w[2], w[3], w[4]);
         if (flag) eta = 0.0;
       }
     }
-    double uL[5], uR[5];
-    for (int k = 0; k < 5; ++k) {
-      uL[k] = G(i - 2 + k); /* cells i-2..i+2: v^- of cell i */
-      uR[k] = G(i - 1 + k); /* cells i-1..i+3: v^+ of cell i+1 */
-    }
+    const double* uL = w;     /* cells i-2..i+2: v^- of cell i */
+    const double* uR = w + 1; /* cells i-1..i+3: v^+ of cell i+1 */
     if (pb->recon == NPO_RBF_ENO3 || pb->recon == NPO_ENO3) {
-      vminus[i + 1] = npo_eno_minus(uL, eta);
-      vplus[i + 1] = npo_eno_plus(uR, eta);
+      *vm = npo_eno_minus(uL, eta);
+      *vp = npo_eno_plus(uR, eta);
     } else {
-      vminus[i + 1] = npo_recon_minus(uL, eta, pb->eps_weno);
-      vplus[i + 1] = npo_recon_plus(uR, eta, pb->eps_weno);
+      *vm = npo_recon_minus(uL, eta, pb->eps_weno);
+      *vp = npo_recon_plus(uR, eta, pb->eps_weno);
     }
-    if (eta_out) eta_out[i + 1] = eta;
-    if (flag_out) flag_out[i + 1] = flag;
   }
-#undef G
+  if (eta_out) *eta_out = eta;
+  if (flag_out) *flag_out = flag;
+}
+
+/* Interface states along one grid line of n cells of one component: for every interface
+ * x_{i+1/2}, i = -1..n-1 (stored at index i+1), the window u_{i-2..i+3} with ghosts per bc. */
+void npo_line_states(const npo_problem* pb, const double* line, long n, double* vminus,
+                     double* vplus, double* eta_out, int* flag_out) {
+  for (long i = -1; i <= n - 1; ++i) {
+    double w[6];
+    for (int k = 0; k < 6; ++k) w[k] = line[ghost(i - 2 + k, n, pb->bc)];
+    interface_states(pb, w, &vminus[i + 1], &vplus[i + 1], eta_out ? &eta_out[i + 1] : NULL,
+                     flag_out ? &flag_out[i + 1] : NULL);
+  }
+}
+
+/* ------------------------------------------------------------------------------------ */
+/* Characteristic-wise reconstruction for the Euler equations (an extension the paper     */
+/* does not use: Example 4 reconstructs as it states the scheme, one scalar field at a    */
+/* time, which the component-wise mode follows).  At each interface the six-cell window   */
+/* of conservative states is projected on the left eigenvectors of the flux Jacobian at   */
+/* the Roe average of the two adjacent cells, every characteristic field is reconstructed */
+/* with the scalar scheme above (eta and the switch on that field), and the edge states    */
+/* are mapped back with the right eigenvectors.                                           */
+/* ------------------------------------------------------------------------------------ */
+
+/* Roe average of two Euler states and the eigen-system of dF/dU (direction dir) there.
+ * Lm (rows = left eigenvectors) and Rm (columns = right eigenvectors) are m x m row-major,
+ * lam the eigenvalues (normal velocity -c, the contact/shear waves, +c).  Returns
+ * NPO_ENONPHYSICAL when a state or the average has rho <= 0, p <= 0 or c^2 <= 0. */
+int npo_char_basis(const npo_problem* pb, int dir, const double* UL, const double* UR, double* Lm, double* Rm,
+                   double* lam) {
+  const int m = pb->ncomp;
+  const double g1 = pb->gamma - 1.0;
+  const double rl = UL[0], rr = UR[0];
+  if (!(rl > 0.0) || !(rr > 0.0)) return NPO_ENONPHYSICAL;
+  const double ul = UL[1] / rl, ur = UR[1] / rr;
+  const double vl = m == 4 ? UL[2] / rl : 0.0, vr = m == 4 ? UR[2] / rr : 0.0;
+  const double El = UL[m - 1], Er = UR[m - 1];
+  double pl, pr;
+  if (m == 4) {
+    pl = g1 * (El - 0.5 * rl * (ul * ul + vl * vl));
+    pr = g1 * (Er - 0.5 * rr * (ur * ur + vr * vr));
+  } else {
+    pl = g1 * (El - 0.5 * rl * ul * ul);
+    pr = g1 * (Er - 0.5 * rr * ur * ur);
+  }
+  if (!(pl > 0.0) || !(pr > 0.0)) return NPO_ENONPHYSICAL;
+  const double Hl = (El + pl) / rl, Hr = (Er + pr) / rr;
+  const double sl = sqrt(rl), sr = sqrt(rr), den = sl + sr;
+  const double u = (sl * ul + sr * ur) / den;
+  const double v = (sl * vl + sr * vr) / den;
+  const double H = (sl * Hl + sr * Hr) / den;
+  const double q2 = m == 4 ? u * u + v * v : u * u;
+  const double c2 = g1 * (H - 0.5 * q2);
+  if (!(c2 > 0.0)) return NPO_ENONPHYSICAL;
+  const double c = sqrt(c2);
+  const double b1 = g1 / c2, b2 = 0.5 * b1 * q2;
+  if (m == 3) {
+    const double R3[9] = {1.0, 1.0, 1.0,
+                          u - c, u, u + c,
+                          H - u * c, 0.5 * q2, H + u * c};
+    const double L3[9] = {0.5 * (b2 + u / c), -0.5 * (b1 * u + 1.0 / c), 0.5 * b1,
+                          1.0 - b2, b1 * u, -b1,
+                          0.5 * (b2 - u / c), -0.5 * (b1 * u - 1.0 / c), 0.5 * b1};
+    memcpy(Rm, R3, sizeof R3);
+    memcpy(Lm, L3, sizeof L3);
+    lam[0] = u - c;
+    lam[1] = u;
+    lam[2] = u + c;
+  } else if (dir == 0) {
+    const double R4[16] = {1.0, 1.0, 0.0, 1.0,
+                           u - c, u, 0.0, u + c,
+                           v, v, 1.0, v,
+                           H - u * c, 0.5 * q2, v, H + u * c};
+    const double L4[16] = {0.5 * (b2 + u / c), -0.5 * (b1 * u + 1.0 / c), -0.5 * b1 * v, 0.5 * b1,
+                           1.0 - b2, b1 * u, b1 * v, -b1,
+                           -v, 0.0, 1.0, 0.0,
+                           0.5 * (b2 - u / c), -0.5 * (b1 * u - 1.0 / c), -0.5 * b1 * v, 0.5 * b1};
+    memcpy(Rm, R4, sizeof R4);
+    memcpy(Lm, L4, sizeof L4);
+    lam[0] = u - c;
+    lam[1] = u;
+    lam[2] = u;
+    lam[3] = u + c;
+  } else {
+    const double R4[16] = {1.0, 1.0, 0.0, 1.0,
+                           u, u, 1.0, u,
+                           v - c, v, 0.0, v + c,
+                           H - v * c, 0.5 * q2, u, H + v * c};
+    const double L4[16] = {0.5 * (b2 + v / c), -0.5 * b1 * u, -0.5 * (b1 * v + 1.0 / c), 0.5 * b1,
+                           1.0 - b2, b1 * u, b1 * v, -b1,
+                           -u, 1.0, 0.0, 0.0,
+                           0.5 * (b2 - v / c), -0.5 * b1 * u, -0.5 * (b1 * v - 1.0 / c), 0.5 * b1};
+    memcpy(Rm, R4, sizeof R4);
+    memcpy(Lm, L4, sizeof L4);
+    lam[0] = v - c;
+    lam[1] = v;
+    lam[2] = v;
+    lam[3] = v + c;
+  }
+  return NPO_OK;
+}
+
+/* Characteristic interface states along one line: lines[c][0..n-1] holds component c.  For
+ * interface i+1/2 (index i+1): W_k = Lm U_k for the window k = i-2..i+3, the scalar interface
+ * states of every field, then U^- = Rm W^-, U^+ = Rm W^+ (sums in component order).  vm, vp are
+ * component-major with n+1 entries per component. */
+static int char_line_states(const npo_problem* pb, int dir, const double* const* lines, long n, double* vm,
+                            double* vp) {
+  const int m = pb->ncomp;
+  for (long i = -1; i <= n - 1; ++i) {
+    double U[6][4], W[4][6], Lm[16], Rm[16], lam[4], wm[4], wp[4];
+    for (int k = 0; k < 6; ++k) {
+      long g = ghost(i - 2 + k, n, pb->bc);
+      for (int c = 0; c < m; ++c) U[k][c] = lines[c][g];
+    }
+    int rc = npo_char_basis(pb, dir, U[2], U[3], Lm, Rm, lam);
+    if (rc) return rc;
+    for (int p = 0; p < m; ++p)
+      for (int k = 0; k < 6; ++k) {
+        double s = Lm[p * m + 0] * U[k][0];
+        for (int c = 1; c < m; ++c) s = s + Lm[p * m + c] * U[k][c];
+        W[p][k] = s;
+      }
+    for (int p = 0; p < m; ++p) interface_states(pb, W[p], &wm[p], &wp[p], NULL, NULL);
+    for (int c = 0; c < m; ++c) {
+      double a = Rm[c * m + 0] * wm[0], b = Rm[c * m + 0] * wp[0];
+      for (int p = 1; p < m; ++p) {
+        a = a + Rm[c * m + p] * wm[p];
+        b = b + Rm[c * m + p] * wp[p];
+      }
+      vm[(size_t)c * (n + 1) + (i + 1)] = a;
+      vp[(size_t)c * (n + 1) + (i + 1)] = b;
+    }
+  }
+  return NPO_OK;
 }
 
 static int validate(const npo_problem* pb) {
@@ -444,6 +562,7 @@ static int validate(const npo_problem* pb) {
   if (!(pb->cfl > 0.0) || !(pb->eps_weno > 0.0) || !(pb->eps_m > 0.0)) return NPO_EINVAL;
   if (pb->recon < NPO_RBF_WENO5 || pb->recon > NPO_ENO2) return NPO_EINVAL;
   if (pb->switch_mode != NPO_SWITCH_MONOTONE && pb->switch_mode != NPO_SWITCH_OFF) return NPO_EINVAL;
+  if (pb->charwise != 0 && (pb->charwise != 1 || pb->flux != NPO_EULER)) return NPO_EINVAL;
   return NPO_OK;
 }
 
@@ -494,11 +613,19 @@ int npo_rhs(const npo_problem* pb, const double* u, double* L, double alpha_out[
   double* vp = (double*)malloc(sizeof(double) * (size_t)(nmax + 1) * (size_t)m);
   double* F = (double*)malloc(sizeof(double) * (size_t)(nmax + 1) * (size_t)m);
 
+  const int charwise = pb->charwise && pb->flux == NPO_EULER;
   /* x sweep: every row j */
   for (long j = 0; j < ny; ++j) {
-    for (int c = 0; c < m; ++c) {
-      for (long i = 0; i < nx; ++i) line[i] = u[c * ncell + j * nx + i];
-      npo_line_states(pb, line, nx, vm + (size_t)c * (nx + 1), vp + (size_t)c * (nx + 1), NULL, NULL);
+    if (charwise) {
+      const double* rows[4];
+      for (int c = 0; c < m; ++c) rows[c] = u + c * ncell + j * nx;
+      rc = char_line_states(pb, 0, rows, nx, vm, vp);
+      if (rc) break;
+    } else {
+      for (int c = 0; c < m; ++c) {
+        for (long i = 0; i < nx; ++i) line[i] = u[c * ncell + j * nx + i];
+        npo_line_states(pb, line, nx, vm + (size_t)c * (nx + 1), vp + (size_t)c * (nx + 1), NULL, NULL);
+      }
     }
     for (long f = 0; f <= nx; ++f) {
       double a[4], b[4], h[4];
@@ -513,12 +640,23 @@ int npo_rhs(const npo_problem* pb, const double* u, double* L, double alpha_out[
       for (long i = 0; i < nx; ++i)
         L[c * ncell + j * nx + i] = -(F[(size_t)c * (nx + 1) + i + 1] - F[(size_t)c * (nx + 1) + i]) / dx;
   }
-  if (pb->dim == 2) {
+  if (pb->dim == 2 && rc == NPO_OK) {
     /* y sweep: every column i, added to the x contribution */
+    double* col = charwise ? (double*)malloc(sizeof(double) * (size_t)ny * (size_t)m) : NULL;
     for (long i = 0; i < nx; ++i) {
-      for (int c = 0; c < m; ++c) {
-        for (long j = 0; j < ny; ++j) line[j] = u[c * ncell + j * nx + i];
-        npo_line_states(pb, line, ny, vm + (size_t)c * (ny + 1), vp + (size_t)c * (ny + 1), NULL, NULL);
+      if (charwise) {
+        const double* cols[4];
+        for (int c = 0; c < m; ++c) {
+          for (long j = 0; j < ny; ++j) col[(size_t)c * ny + j] = u[c * ncell + j * nx + i];
+          cols[c] = col + (size_t)c * ny;
+        }
+        rc = char_line_states(pb, 1, cols, ny, vm, vp);
+        if (rc) break;
+      } else {
+        for (int c = 0; c < m; ++c) {
+          for (long j = 0; j < ny; ++j) line[j] = u[c * ncell + j * nx + i];
+          npo_line_states(pb, line, ny, vm + (size_t)c * (ny + 1), vp + (size_t)c * (ny + 1), NULL, NULL);
+        }
       }
       for (long f = 0; f <= ny; ++f) {
         double a[4], b[4], h[4];
@@ -534,12 +672,13 @@ int npo_rhs(const npo_problem* pb, const double* u, double* L, double alpha_out[
           L[c * ncell + j * nx + i] =
               L[c * ncell + j * nx + i] - (F[(size_t)c * (ny + 1) + j + 1] - F[(size_t)c * (ny + 1) + j]) / dy;
     }
+    free(col);
   }
   free(line);
   free(vm);
   free(vp);
   free(F);
-  return NPO_OK;
+  return rc;
 }
 
 /* Time step: dt = CFL dx / alpha in 1D, CFL / (alpha_x/dx + alpha_y/dy) in 2D, clipped to

@@ -31,6 +31,7 @@ typedef struct {
   int recon;       /* NPO_* reconstruction (k = 3 or k = 2; the non-RBF ones have eta = 0) */
   int switch_mode; /* NPO_SWITCH_MONOTONE or NPO_SWITCH_OFF */
   double dt_fixed; /* > 0: fixed time step instead of the CFL rule */
+  int charwise;    /* Euler only: 1 = reconstruct characteristic fields (Roe average), 0 = components */
 } npo_problem;
 
 void npo_table3(double c[12], double p[12]);
@@ -52,6 +53,8 @@ double npo_eno2_minus(const double u3[3], double eta);
 double npo_eno2_plus(const double u3[3], double eta);
 void npo_line_states(const npo_problem* pb, const double* line, long n, double* vminus,
                      double* vplus, double* eta_out, int* flag_out);
+int npo_char_basis(const npo_problem* pb, int dir, const double* UL, const double* UR, double* Lm, double* Rm,
+                   double* lam);
 int npo_alpha(const npo_problem* pb, const double* u, double alpha[2]);
 int npo_rhs(const npo_problem* pb, const double* u, double* L, double alpha_out[2]);
 int npo_step(const npo_problem* pb, double* u, double T, double* t, double* dt_out);
