@@ -40,7 +40,7 @@
 extern "C" {
 #endif
 
-#define NPW_ABI_VERSION 1
+#define NPW_ABI_VERSION 2
 
 enum {
   NPW_OK = 0,
@@ -66,6 +66,12 @@ enum {
   NPW_RBF_WENO3 = 4, NPW_WENO3_JS = 5, NPW_RBF_ENO2 = 6, NPW_ENO2 = 7
 };
 enum { NPW_SWITCH_MONOTONE = 0, NPW_SWITCH_OFF = 1 };        /* Section 4 switch on / off */
+/* Variables the Euler equations are reconstructed in.  Component-wise is the scheme as the paper
+ * applies it to systems (Example 4).  Characteristic-wise (an extension) projects each
+ * interface's six-cell window on the left eigenvectors of the flux Jacobian at the Roe average of
+ * the two adjacent cells, reconstructs every characteristic field with the scalar scheme (its own
+ * shape parameter and switch) and maps the edge states back with the right eigenvectors. */
+enum { NPW_COMPONENTWISE = 0, NPW_CHARACTERISTIC = 1 };
 
 typedef struct {
   int32_t abi_version; /* must be NPW_ABI_VERSION */
@@ -84,6 +90,8 @@ typedef struct {
   double eps_weno;         /* epsilon of the nonlinear weights, Section 2 (1e-6) */
   double eps_m;            /* eps_M of the eta denominator (> 0), added with its sign (1e-12) */
   double dt_fixed;         /* > 0: use this dt instead of the CFL rule (accuracy studies) */
+  int32_t variables;       /* NPW_COMPONENTWISE or NPW_CHARACTERISTIC (NPW_EULER only) */
+  int32_t reserved;        /* must be 0 */
 } npw_params;
 
 typedef struct {
@@ -166,10 +174,11 @@ int npweno_launch_shape(const npw_solver* s, int32_t* block_1d, int32_t* tile_x,
 
 /* ---- Serving (continuous batching) -------------------------------------------------------- */
 /* A request loop for mixed 1D solves.  All requests share one device arena of
- * hbm_budget_bytes (split into the three state buffers) and max_slots slots per flux type.
+ * hbm_budget_bytes (split into the three state buffers) and max_slots slots per pool (one pool
+ * each for advection, Burgers, component-wise Euler and characteristic-wise Euler).
  * Submitted requests wait in a FIFO queue; npw_server_pump admits the head of the queue as
  * soon as a slot and a large enough arena range are free, then advances every running request
- * by `steps` RK steps with one launch of the batched stage kernel per flux type and stage
+ * by `steps` RK steps with one launch of the batched stage kernel per pool and stage
  * (their work overlaps on the device), and retires the finished ones.  A request's result is
  * bit-identical to solving it alone with npweno_create/npweno_solve in the same precision.
  * Requests never fail one another: a request that becomes non-finite or non-physical is

@@ -126,6 +126,7 @@ def lib():
         L.npo_eta2.restype = ctypes.c_double
         L.npo_line_states.argtypes = [P, _D, ctypes.c_long, _D, _D, _D, _I]
         L.npo_char_basis.argtypes = [P, ctypes.c_int, _D, _D, _D, _D, _D]
+        L.npo_char_interface.argtypes = [P, ctypes.c_int, _D, _D, _D]
         L.npo_alpha.argtypes = [P, _D, _D]
         L.npo_alpha.restype = ctypes.c_int
         L.npo_rhs.argtypes = [P, _D, _D, _D]
@@ -232,6 +233,19 @@ def char_basis(pb: Problem, direction: int, UL, UR):
     if rc:
         raise OracleError(rc)
     return Lm.reshape(m, m), Rm.reshape(m, m), lam
+
+
+def char_interface(pb: Problem, direction: int, U6):
+    """(v^-, v^+) at one interface from its six-cell window U6[k, c] (cells i-2..i+3),
+    characteristic-wise."""
+    m = pb.ncomp
+    U6 = _f64(U6).reshape(6, m).copy()
+    vm, vp = np.zeros(m), np.zeros(m)
+    p = pb.c()
+    rc = lib().npo_char_interface(ctypes.byref(p), direction, _dp(U6), _dp(vm), _dp(vp))
+    if rc:
+        raise OracleError(rc)
+    return vm, vp
 
 
 def alpha(pb: Problem, u):

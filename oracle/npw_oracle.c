@@ -510,6 +510,34 @@ int npo_char_basis(const npo_problem* pb, int dir, const double* UL, const doubl
   return NPO_OK;
 }
 
+/* States at one interface from its six-cell window of conservative states U6[k*m + c]
+ * (k = cells i-2..i+3): the characteristic-wise counterpart of interface_states. */
+int npo_char_interface(const npo_problem* pb, int dir, const double* U6, double* vm, double* vp) {
+  const int m = pb->ncomp;
+  double U[6][4], W[4][6], Lm[16], Rm[16], lam[4], wm[4], wp[4];
+  for (int k = 0; k < 6; ++k)
+    for (int c = 0; c < m; ++c) U[k][c] = U6[k * m + c];
+  int rc = npo_char_basis(pb, dir, U[2], U[3], Lm, Rm, lam);
+  if (rc) return rc;
+  for (int p = 0; p < m; ++p)
+    for (int k = 0; k < 6; ++k) {
+      double s = Lm[p * m + 0] * U[k][0];
+      for (int c = 1; c < m; ++c) s = s + Lm[p * m + c] * U[k][c];
+      W[p][k] = s;
+    }
+  for (int p = 0; p < m; ++p) interface_states(pb, W[p], &wm[p], &wp[p], NULL, NULL);
+  for (int c = 0; c < m; ++c) {
+    double a = Rm[c * m + 0] * wm[0], b = Rm[c * m + 0] * wp[0];
+    for (int p = 1; p < m; ++p) {
+      a = a + Rm[c * m + p] * wm[p];
+      b = b + Rm[c * m + p] * wp[p];
+    }
+    vm[c] = a;
+    vp[c] = b;
+  }
+  return NPO_OK;
+}
+
 /* Characteristic interface states along one line: lines[c][0..n-1] holds component c.  For
  * interface i+1/2 (index i+1): W_k = Lm U_k for the window k = i-2..i+3, the scalar interface
  * states of every field, then U^- = Rm W^-, U^+ = Rm W^+ (sums in component order).  vm, vp are

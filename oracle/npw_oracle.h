@@ -55,6 +55,7 @@ void npo_line_states(const npo_problem* pb, const double* line, long n, double* 
                      double* vplus, double* eta_out, int* flag_out);
 int npo_char_basis(const npo_problem* pb, int dir, const double* UL, const double* UR, double* Lm, double* Rm,
                    double* lam);
+int npo_char_interface(const npo_problem* pb, int dir, const double* U6, double* vm, double* vp);
 int npo_alpha(const npo_problem* pb, const double* u, double alpha[2]);
 int npo_rhs(const npo_problem* pb, const double* u, double* L, double alpha_out[2]);
 int npo_step(const npo_problem* pb, double* u, double T, double* t, double* dt_out);

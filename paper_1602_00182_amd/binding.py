@@ -14,13 +14,15 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libnpweno.so")
 
-NPW_ABI_VERSION = 1
+NPW_ABI_VERSION = 2
 OK, EINVAL, ENOMEM, EHIP, ENONFINITE, ENONPHYSICAL, EBUSY, ENOTFOUND = 0, -1, -2, -3, -4, -5, -6, -7
 ADVECTION, BURGERS, EULER = 0, 1, 2
 PERIODIC, TRANSMISSIVE = 0, 1
 FP64, FP32 = 0, 1
-RBF_WENO5, WENO5_JS, RBF_ENO3, ENO3 = 0, 1, 2, 3
+RBF_WENO5, WENO5_JS, RBF_ENO3, ENO3 = 0, 1, 2, 3  # k = 3
+RBF_WENO3, WENO3_JS, RBF_ENO2, ENO2 = 4, 5, 6, 7  # k = 2
 SWITCH_MONOTONE, SWITCH_OFF = 0, 1
+COMPONENTWISE, CHARACTERISTIC = 0, 1
 
 
 class Params(ctypes.Structure):
@@ -32,7 +34,7 @@ class Params(ctypes.Structure):
         ("x0", ctypes.c_double), ("x1", ctypes.c_double), ("y0", ctypes.c_double), ("y1", ctypes.c_double),
         ("speed_x", ctypes.c_double), ("speed_y", ctypes.c_double), ("gamma", ctypes.c_double),
         ("cfl", ctypes.c_double), ("eps_weno", ctypes.c_double), ("eps_m", ctypes.c_double),
-        ("dt_fixed", ctypes.c_double),
+        ("dt_fixed", ctypes.c_double), ("variables", ctypes.c_int32), ("reserved", ctypes.c_int32),
     ]
 
 

@@ -26,22 +26,55 @@ __device__ __forceinline__ int ghost_index(int k, int n, int bc) {
   return k < 0 ? 0 : n - 1;
 }
 
+// Correctly rounded double division (round to nearest, ties to even).  The instruction
+// sequence behind the '/' operator keeps the quotient within one unit in the last place but can
+// return the neighbour of the nearest double (observed on operands of the scheme).  The residual
+// a - q b is exact for a faithful q (one fused multiply-add), so comparing it with the residual
+// of the neighbour on the side of the exact quotient picks the nearest double.  Zero, subnormal,
+// huge and non-finite operands or quotients keep the hardware result.
+__device__ __forceinline__ double div_rn(double a, double b) {
+  const double q = a / b;
+  const double aq = fabs(q), aa = fabs(a), ab = fabs(b);
+  if (!(aq > 0x1p-900 && aq < 0x1p900 && aa > 0x1p-900 && aa < 0x1p900 && ab > 0x1p-900 && ab < 0x1p900)) return q;
+  const double r = fma(-q, b, a);
+  if (r == 0.0) return q;
+  const bool up = (r > 0.0) == (b > 0.0);  // the exact quotient lies above q
+  const long long bits = __double_as_longlong(q);
+  const long long nb = ((q > 0.0) == up) ? bits + 1 : bits - 1;
+  const double q1 = __longlong_as_double(nb);
+  const double e0 = fabs(r), e1 = fabs(fma(-q1, b, a));
+  if (e1 < e0 || (e1 == e0 && (nb & 1) == 0)) return q1;
+  return q;
+}
+// Division in the bulk precision: correctly rounded in double (the exact flavour), the plain
+// operator in float.
+template <typename R>
+__device__ __forceinline__ R fdiv(R a, R b) {
+  if constexpr (sizeof(R) == 8)
+    return div_rn(a, b);
+  else
+    return a / b;
+}
+
 // Monotone-polynomial test of Section 4 (eqs. root_value and adaptation) on the window
 // (u_{j-1}, u_j, u_{j+1}): the quadratic reconstruction has its extremum at
 // x_p/dx = (-2u_{j-1} + 3u_j - u_{j+1}) / (-u_{j-1} + 2u_j - u_{j+1}) from x_{j-3/2}; the window is
 // not monotone when 0 < x_p/dx < 3.  Division by zero (linear data) gives inf/NaN, which fails
 // the strict test.  Double precision, uncontracted: the decision is the one the quotient makes.
+// CR: correctly rounded quotient (double bulk); otherwise the hardware quotient.
+template <bool CR = true>
 __device__ __forceinline__ int monotone_flag(double um1, double u0, double up1) {
 #pragma clang fp contract(off)
   double num = -2.0 * um1 + 3.0 * u0 - up1;
   double den = -um1 + 2.0 * u0 - up1;
-  double xp = num / den;
+  double xp = CR ? div_rn(num, den) : num / den;
   return (xp > 0.0 && xp < 3.0) ? 1 : 0;
 }
 
 // Shape parameter eta = eps^2 dx^2 at x_{i+1/2} (Table 3 caption) from u_{i-1}..u_{i+2}:
 // third over (weighted) first undivided difference; eps_M is added with the sign of the
 // denominator so that it never crosses zero.  Double precision, uncontracted.
+template <bool CR = true>
 __device__ __forceinline__ double eta_ratio(double um1, double u0, double up1, double up2, double eps_m) {
 #pragma clang fp contract(off)
   double num = um1 - 3.0 * u0 + 3.0 * up1 - up2;
@@ -50,7 +83,7 @@ __device__ __forceinline__ double eta_ratio(double um1, double u0, double up1, d
     den = den + eps_m;
   else
     den = den - eps_m;
-  return num / den;
+  return CR ? div_rn(num, den) : num / den;
 }
 
 // Jiang-Shu smoothness indicators of cell i from (a..e) = u_{i-2}..u_{i+2}; b0 for the stencil
@@ -121,9 +154,9 @@ __device__ __forceinline__ double weno_minus_exact(double a, double b, double c,
   double q0 = table3_row<double, 0>(c, d, e, eta);
   double q1 = table3_row<double, 1>(b, c, d, eta);
   double q2 = table3_row<double, 2>(a, b, c, eta);
-  double a0 = (3.0 / 10.0) / s0, a1 = (3.0 / 5.0) / s1, a2 = (1.0 / 10.0) / s2;
+  double a0 = div_rn(3.0 / 10.0, s0), a1 = div_rn(3.0 / 5.0, s1), a2 = div_rn(1.0 / 10.0, s2);
   double s = a0 + a1 + a2;
-  double w0 = a0 / s, w1 = a1 / s, w2 = a2 / s;
+  double w0 = div_rn(a0, s), w1 = div_rn(a1, s), w2 = div_rn(a2, s);
   return w0 * q0 + w1 * q1 + w2 * q2;
 }
 __device__ __forceinline__ double weno_plus_exact(double a, double b, double c, double d, double e, double eta,
@@ -132,9 +165,9 @@ __device__ __forceinline__ double weno_plus_exact(double a, double b, double c, 
   double q0 = table3_row<double, -1>(c, d, e, eta);
   double q1 = table3_row<double, 0>(b, c, d, eta);
   double q2 = table3_row<double, 1>(a, b, c, eta);
-  double a0 = (1.0 / 10.0) / s0, a1 = (3.0 / 5.0) / s1, a2 = (3.0 / 10.0) / s2;
+  double a0 = div_rn(1.0 / 10.0, s0), a1 = div_rn(3.0 / 5.0, s1), a2 = div_rn(3.0 / 10.0, s2);
   double s = a0 + a1 + a2;
-  double w0 = a0 / s, w1 = a1 / s, w2 = a2 / s;
+  double w0 = div_rn(a0, s), w1 = div_rn(a1, s), w2 = div_rn(a2, s);
   return w0 * q0 + w1 * q1 + w2 * q2;
 }
 // Fast float flavour: i_r = 1 / s_r precomputed, one reciprocal for the normalisation.
@@ -241,6 +274,7 @@ __device__ __forceinline__ R table2_row(R w0, R w1, R eta) {
 // value, eps_M added with the sign of the denominator.  For the right edge of cell i pass
 // (u_{i-1}, u_i, u_{i+1}); for its left edge the mirror (u_{i+1}, u_i, u_{i-1}).  Double,
 // uncontracted.
+template <bool CR = true>
 __device__ __forceinline__ double eta2_ratio(double ufar, double u0, double unear, double eps_m) {
 #pragma clang fp contract(off)
   double num = 2.0 * (-ufar + 2.0 * u0 - unear);
@@ -249,7 +283,7 @@ __device__ __forceinline__ double eta2_ratio(double ufar, double u0, double unea
     den = den + eps_m;
   else
     den = den - eps_m;
-  return num / den;
+  return CR ? div_rn(num, den) : num / den;
 }
 
 // WENO3 edge values of cell i from (a, b, c) = u_{i-1}, u_i, u_{i+1}: v^-_{i+1/2} combines row 0 on
@@ -264,10 +298,10 @@ __device__ __forceinline__ double weno3_exact(double a, double b, double c, doub
   t = b - a;
   const double b1 = t * t;
   const double d0 = PLUS ? 1.0 / 3.0 : 2.0 / 3.0, d1 = PLUS ? 2.0 / 3.0 : 1.0 / 3.0;
-  const double a0 = d0 / ((eps + b0) * (eps + b0));
-  const double a1 = d1 / ((eps + b1) * (eps + b1));
+  const double a0 = div_rn(d0, (eps + b0) * (eps + b0));
+  const double a1 = div_rn(d1, (eps + b1) * (eps + b1));
   const double s = a0 + a1;
-  const double w0 = a0 / s, w1 = a1 / s;
+  const double w0 = div_rn(a0, s), w1 = div_rn(a1, s);
   if (PLUS)
     return w0 * table2_row<double, -1>(b, c, eta) + w1 * table2_row<double, 0>(a, b, eta);
   return w0 * table2_row<double, 0>(b, c, eta) + w1 * table2_row<double, 1>(a, b, eta);
@@ -302,6 +336,157 @@ __device__ __forceinline__ R eno2(int r, R a, R b, R c, R eta) {
   return PLUS ? table2_row<R, 0>(a, b, eta) : table2_row<R, 1>(a, b, eta);
 }
 
+// States at one interface x_{i+1/2} of one scalar field from its six-cell window
+// w = u_{i-2}..u_{i+3} (register form of the LDS phases above, used where the field is local to
+// the interface, as in characteristic-wise reconstruction): v^- of cell i and v^+ of cell i+1
+// with the shape parameter(s) and switch of the reconstruction mode.  wd holds the same window in
+// double for the shape parameter, the switch and the ENO stencil choice.
+template <typename R>
+__device__ __forceinline__ void window_states(const R* w, const double* wd, const ReconMode rm, R eps, double eps_m,
+                                              R& vm, R& vp) {
+  constexpr bool kCR = sizeof(R) == 8;
+  if (rm.k2) {
+    double el = 0.0, er = 0.0;
+    if (rm.use_eta) {
+      el = eta2_ratio<kCR>(wd[1], wd[2], wd[3], eps_m);  // right edge of cell i
+      er = eta2_ratio<kCR>(wd[4], wd[3], wd[2], eps_m);  // left edge of cell i+1 (mirror)
+      if (rm.use_switch) {
+        if (monotone_flag<kCR>(wd[1], wd[2], wd[3])) el = 0.0;
+        if (monotone_flag<kCR>(wd[2], wd[3], wd[4])) er = 0.0;
+      }
+    }
+    if (rm.eno) {
+      vm = eno2<R, false>(eno2_stencil(wd[1], wd[2], wd[3]), w[1], w[2], w[3], R(el));
+      vp = eno2<R, true>(eno2_stencil(wd[2], wd[3], wd[4]), w[2], w[3], w[4], R(er));
+    } else {
+      vm = weno3<R, false>(w[1], w[2], w[3], R(el), eps);
+      vp = weno3<R, true>(w[2], w[3], w[4], R(er), eps);
+    }
+    return;
+  }
+  double e = 0.0;
+  if (rm.use_eta) {
+    e = eta_ratio<kCR>(wd[1], wd[2], wd[3], wd[4], eps_m);
+    if (rm.use_switch && (monotone_flag<kCR>(wd[1], wd[2], wd[3]) | monotone_flag<kCR>(wd[2], wd[3], wd[4]))) e = 0.0;
+  }
+  const R eta = R(e);
+  if (rm.eno) {
+    vm = eno_minus<R>(eno_stencil(wd[0], wd[1], wd[2], wd[3], wd[4]), w[0], w[1], w[2], w[3], w[4], eta);
+    vp = eno_plus<R>(eno_stencil(wd[1], wd[2], wd[3], wd[4], wd[5]), w[1], w[2], w[3], w[4], w[5], eta);
+  } else {
+    R s0, s1, s2;
+    weight_denominators<R>(w[0], w[1], w[2], w[3], w[4], eps, s0, s1, s2);
+    vm = weno_minus<R>(w[0], w[1], w[2], w[3], w[4], eta, s0, s1, s2);
+    weight_denominators<R>(w[1], w[2], w[3], w[4], w[5], eps, s0, s1, s2);
+    vp = weno_plus<R>(w[1], w[2], w[3], w[4], w[5], eta, s0, s1, s2);
+  }
+}
+
+// Eigen-system of the Euler flux Jacobian along DIR at the Roe average of the states UL, UR
+// (conservative; M = 3 in 1D, 4 in 2D): Lm rows are left eigenvectors, Rm columns right
+// eigenvectors, for the waves (normal velocity - c, contact [, shear], + c).  The double flavour
+// evaluates every entry in the order written, uncontracted, so it reproduces a plain evaluation
+// of the same formulas bit for bit.
+template <typename R, int M, int DIR>
+__device__ __forceinline__ void char_basis(const R* UL, const R* UR, R gamma, R (&Lm)[M][M], R (&Rm)[M][M]) {
+#pragma clang fp contract(off)
+  const R g1 = gamma - R(1.0);
+  const R rl = UL[0], rr = UR[0];
+  const R ul = fdiv(UL[1], rl), ur = fdiv(UR[1], rr);
+  const R El = UL[M - 1], Er = UR[M - 1];
+  R u, v = R(0), pl, pr;
+  if constexpr (M == 4) {
+    const R vl = fdiv(UL[2], rl), vr = fdiv(UR[2], rr);
+    pl = g1 * (El - R(0.5) * rl * (ul * ul + vl * vl));
+    pr = g1 * (Er - R(0.5) * rr * (ur * ur + vr * vr));
+    const R sl = sqrt(rl), sr = sqrt(rr), den = sl + sr;
+    u = fdiv(sl * ul + sr * ur, den);
+    v = fdiv(sl * vl + sr * vr, den);
+  } else {
+    pl = g1 * (El - R(0.5) * rl * ul * ul);
+    pr = g1 * (Er - R(0.5) * rr * ur * ur);
+    const R sl = sqrt(rl), sr = sqrt(rr), den = sl + sr;
+    u = fdiv(sl * ul + sr * ur, den);
+  }
+  const R Hl = fdiv(El + pl, rl), Hr = fdiv(Er + pr, rr);
+  const R sl = sqrt(rl), sr = sqrt(rr), den = sl + sr;
+  const R H = fdiv(sl * Hl + sr * Hr, den);
+  const R q2 = M == 4 ? u * u + v * v : u * u;
+  const R c2 = g1 * (H - R(0.5) * q2);
+  const R c = sqrt(c2);
+  const R b1 = fdiv(g1, c2), b2 = R(0.5) * b1 * q2;
+  const R un = DIR == 0 ? u : v;  // normal velocity
+  const R ic = fdiv(R(1.0), c);
+  const R uc = fdiv(un, c);
+  if constexpr (M == 3) {
+    Rm[0][0] = R(1.0), Rm[0][1] = R(1.0), Rm[0][2] = R(1.0);
+    Rm[1][0] = u - c, Rm[1][1] = u, Rm[1][2] = u + c;
+    Rm[2][0] = H - u * c, Rm[2][1] = R(0.5) * q2, Rm[2][2] = H + u * c;
+    Lm[0][0] = R(0.5) * (b2 + uc), Lm[0][1] = R(-0.5) * (b1 * u + ic), Lm[0][2] = R(0.5) * b1;
+    Lm[1][0] = R(1.0) - b2, Lm[1][1] = b1 * u, Lm[1][2] = -b1;
+    Lm[2][0] = R(0.5) * (b2 - uc), Lm[2][1] = R(-0.5) * (b1 * u - ic), Lm[2][2] = R(0.5) * b1;
+  } else if constexpr (DIR == 0) {
+    Rm[0][0] = R(1.0), Rm[0][1] = R(1.0), Rm[0][2] = R(0.0), Rm[0][3] = R(1.0);
+    Rm[1][0] = u - c, Rm[1][1] = u, Rm[1][2] = R(0.0), Rm[1][3] = u + c;
+    Rm[2][0] = v, Rm[2][1] = v, Rm[2][2] = R(1.0), Rm[2][3] = v;
+    Rm[3][0] = H - u * c, Rm[3][1] = R(0.5) * q2, Rm[3][2] = v, Rm[3][3] = H + u * c;
+    Lm[0][0] = R(0.5) * (b2 + uc), Lm[0][1] = R(-0.5) * (b1 * u + ic), Lm[0][2] = R(-0.5) * b1 * v,
+    Lm[0][3] = R(0.5) * b1;
+    Lm[1][0] = R(1.0) - b2, Lm[1][1] = b1 * u, Lm[1][2] = b1 * v, Lm[1][3] = -b1;
+    Lm[2][0] = -v, Lm[2][1] = R(0.0), Lm[2][2] = R(1.0), Lm[2][3] = R(0.0);
+    Lm[3][0] = R(0.5) * (b2 - uc), Lm[3][1] = R(-0.5) * (b1 * u - ic), Lm[3][2] = R(-0.5) * b1 * v,
+    Lm[3][3] = R(0.5) * b1;
+  } else {
+    Rm[0][0] = R(1.0), Rm[0][1] = R(1.0), Rm[0][2] = R(0.0), Rm[0][3] = R(1.0);
+    Rm[1][0] = u, Rm[1][1] = u, Rm[1][2] = R(1.0), Rm[1][3] = u;
+    Rm[2][0] = v - c, Rm[2][1] = v, Rm[2][2] = R(0.0), Rm[2][3] = v + c;
+    Rm[3][0] = H - v * c, Rm[3][1] = R(0.5) * q2, Rm[3][2] = u, Rm[3][3] = H + v * c;
+    Lm[0][0] = R(0.5) * (b2 + uc), Lm[0][1] = R(-0.5) * b1 * u, Lm[0][2] = R(-0.5) * (b1 * v + ic),
+    Lm[0][3] = R(0.5) * b1;
+    Lm[1][0] = R(1.0) - b2, Lm[1][1] = b1 * u, Lm[1][2] = b1 * v, Lm[1][3] = -b1;
+    Lm[2][0] = -u, Lm[2][1] = R(1.0), Lm[2][2] = R(0.0), Lm[2][3] = R(0.0);
+    Lm[3][0] = R(0.5) * (b2 - uc), Lm[3][1] = R(-0.5) * b1 * u, Lm[3][2] = R(-0.5) * (b1 * v - ic),
+    Lm[3][3] = R(0.5) * b1;
+  }
+}
+
+// Characteristic-wise interface states from the six-cell window U[k][c] (k = cells i-2..i+3):
+// project on the left eigenvectors at the Roe average of cells i and i+1, reconstruct each field,
+// map the edge values back with the right eigenvectors (sums in component order).
+template <typename R, int M, int DIR>
+__device__ __forceinline__ void char_states(const R (&U)[6][M], R gamma, const ReconMode rm, R eps, double eps_m,
+                                            R* A, R* B) {
+#pragma clang fp contract(off)
+  R Lm[M][M], Rm[M][M];
+  char_basis<R, M, DIR>(U[2], U[3], gamma, Lm, Rm);
+  R wm[M], wp[M];
+#pragma unroll
+  for (int p = 0; p < M; ++p) {
+    R w[6];
+    double wd[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+      R s = Lm[p][0] * U[k][0];
+#pragma unroll
+      for (int c = 1; c < M; ++c) s = s + Lm[p][c] * U[k][c];
+      w[k] = s;
+      wd[k] = double(s);
+    }
+    window_states<R>(w, wd, rm, eps, eps_m, wm[p], wp[p]);
+  }
+#pragma unroll
+  for (int c = 0; c < M; ++c) {
+    R a = Rm[c][0] * wm[0], b = Rm[c][0] * wp[0];
+#pragma unroll
+    for (int p = 1; p < M; ++p) {
+      a = a + Rm[c][p] * wm[p];
+      b = b + Rm[c][p] * wp[p];
+    }
+    A[c] = a;
+    B[c] = b;
+  }
+}
+
 // Physical flux along direction DIR (0: x, 1: y) of the state U[0..M-1] (Section 5.1; Euler as in
 // Example 4, conservative variables).
 template <typename R, int FLUX, int M, int DIR>
@@ -312,14 +497,14 @@ __device__ __forceinline__ void phys_flux(const R* U, R speed, R gamma, R* F) {
     F[0] = R(0.5) * U[0] * U[0];
   } else if constexpr (M == 3) {
     R rho = U[0], m = U[1], E = U[2];
-    R u = m / rho;
+    R u = fdiv(m, rho);
     R p = (gamma - R(1.0)) * (E - R(0.5) * rho * u * u);
     F[0] = m;
     F[1] = m * u + p;
     F[2] = (E + p) * u;
   } else {
     R rho = U[0], mx = U[1], my = U[2], E = U[3];
-    R u = mx / rho, v = my / rho;
+    R u = fdiv(mx, rho), v = fdiv(my, rho);
     R p = (gamma - R(1.0)) * (E - R(0.5) * rho * (u * u + v * v));
     if constexpr (DIR == 0) {
       F[0] = mx;
@@ -359,21 +544,21 @@ __device__ __forceinline__ R spectral_radius(const R* U, R speed, R gamma, int& 
   } else if constexpr (FLUX == kBurgers) {
     return fabs(U[0]);
   } else if constexpr (M == 3) {
-    R rho = U[0], u = U[1] / rho;
+    R rho = U[0], u = fdiv(U[1], rho);
     R p = (gamma - R(1.0)) * (U[2] - R(0.5) * rho * u * u);
     if (!(rho > R(0)) || !(p > R(0))) {
       bad = 2;
       return R(0);
     }
-    return fabs(u) + sqrt(gamma * p / rho);
+    return fabs(u) + sqrt(fdiv(gamma * p, rho));
   } else {
-    R rho = U[0], u = U[1] / rho, v = U[2] / rho;
+    R rho = U[0], u = fdiv(U[1], rho), v = fdiv(U[2], rho);
     R p = (gamma - R(1.0)) * (U[3] - R(0.5) * rho * (u * u + v * v));
     if (!(rho > R(0)) || !(p > R(0))) {
       bad = 2;
       return R(0);
     }
-    return fabs(DIR == 0 ? u : v) + sqrt(gamma * p / rho);
+    return fabs(DIR == 0 ? u : v) + sqrt(fdiv(gamma * p, rho));
   }
 }
 
@@ -386,9 +571,9 @@ __device__ __forceinline__ double step_dt(double dt_fixed, double cfl, double dx
   if (dt_fixed > 0.0)
     dt = dt_fixed;
   else if constexpr (DIM == 1)
-    dt = cfl * dx / ax;
+    dt = div_rn(cfl * dx, ax);
   else
-    dt = cfl / (ax / dx + ay / dy);
+    dt = div_rn(cfl, div_rn(ax, dx) + div_rn(ay, dy));
   double rem = T - t;
   if (dt > rem) dt = rem;
   return dt;

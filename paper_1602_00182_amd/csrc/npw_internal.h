@@ -66,6 +66,7 @@ struct StageArgs {
   void* C;   // u^(2) buffer
   void* out; // rhs mode: destination of L(u)
   int stage; // 1, 2, 3: SSP-RK3 stage; 0: evaluate L(u^n) into out
+  int charw; // Euler: 1 = characteristic-wise reconstruction (same for every instance of a launch)
   // Single-grid solvers spread each alpha slot over kSpread cache lines so that hundreds of
   // workgroups do not queue on one atomic: entry (slot, dir, k) lives at
   // spread[((slot * 2 + dir) * kSpread + k) * kSpreadStride].  Null for batches (they use

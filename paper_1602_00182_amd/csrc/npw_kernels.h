@@ -21,7 +21,7 @@
 
 namespace npw {
 
-template <typename R, int FLUX, int M, int BS>
+template <typename R, int FLUX, int M, int BS, bool CHAR>
 __device__ __forceinline__ void stage1d_tile(const StageArgs& a, const Tile tile) {
   constexpr bool kExact = std::is_same<R, double>::value;
   constexpr int W = BS + 4;  // LDS cells per component: start-3 .. start+BS
@@ -165,19 +165,20 @@ __device__ __forceinline__ void stage1d_tile(const StageArgs& a, const Tile tile
 
   // ---- cell phase: cell start-1+tid (LDS window tid..tid+4) -------------------------------
   // Section 4 monotone flag of the window centred on the cell, and the three weight
-  // denominators (eps + beta_r)^2 of the cell.
+  // denominators (eps + beta_r)^2 of the cell.  (Characteristic fields belong to an interface,
+  // so that mode does all of its work in the interface phase.)
 #pragma unroll
-  for (int c = 0; c < M; ++c) {
+  for (int c = 0; c < (CHAR ? 0 : M); ++c) {
     // bit 0: switch flag; bits 1-2: ENO stencil
-    int fl = use_switch ? monotone_flag(D(c, tid + 1), D(c, tid + 2), D(c, tid + 3)) : 0;
+    int fl = use_switch ? monotone_flag<kExact>(D(c, tid + 1), D(c, tid + 2), D(c, tid + 3)) : 0;
     if (k2) {
       // k = 2: the cell's ENO2 stencil, and its right- and left-edge shape parameters (zero
       // when the cell's window is flagged), kept in the denominator slots 0 and 1
       if (eno) fl |= eno2_stencil(D(c, tid + 1), D(c, tid + 2), D(c, tid + 3)) << 1;
       double er = 0.0, el = 0.0;
       if (use_eta && !(fl & 1)) {
-        er = eta2_ratio(D(c, tid + 1), D(c, tid + 2), D(c, tid + 3), eps_m);
-        el = eta2_ratio(D(c, tid + 3), D(c, tid + 2), D(c, tid + 1), eps_m);
+        er = eta2_ratio<kExact>(D(c, tid + 1), D(c, tid + 2), D(c, tid + 3), eps_m);
+        el = eta2_ratio<kExact>(D(c, tid + 3), D(c, tid + 2), D(c, tid + 1), eps_m);
       }
       s_den[c][0][tid] = R(er);
       s_den[c][1][tid] = R(el);
@@ -199,8 +200,16 @@ __device__ __forceinline__ void stage1d_tile(const StageArgs& a, const Tile tile
   // and the global Lax-Friedrichs flux.
   if (tid < BS - 1) {
     R A[M], B[M], H[M];
+    if constexpr (CHAR) {  // cells i-2..i+3 of interface i+1/2 are LDS tid..tid+5
+      R U[6][M];
 #pragma unroll
-    for (int c = 0; c < M; ++c) {
+      for (int k = 0; k < 6; ++k)
+#pragma unroll
+        for (int c = 0; c < M; ++c) U[k][c] = s_u[c][tid + k];
+      char_states<R, M, 0>(U, gamma, rm, eps, eps_m, A, B);
+    }
+#pragma unroll
+    for (int c = 0; c < (CHAR ? 0 : M); ++c) {
       if (k2) {  // left cell LDS tid+2, right cell tid+3; each edge with its own cell's eta
         const R el = s_den[c][0][tid], er = s_den[c][1][tid + 1];
         if (eno) {
@@ -214,7 +223,7 @@ __device__ __forceinline__ void stage1d_tile(const StageArgs& a, const Tile tile
       }
       double e = 0.0;
       if (use_eta) {
-        e = eta_ratio(D(c, tid + 1), D(c, tid + 2), D(c, tid + 3), D(c, tid + 4), eps_m);
+        e = eta_ratio<kExact>(D(c, tid + 1), D(c, tid + 2), D(c, tid + 3), D(c, tid + 4), eps_m);
         if (use_switch && ((s_flag[c][tid] | s_flag[c][tid + 1]) & 1)) e = 0.0;
       }
       const R eta = R(e);
@@ -244,7 +253,7 @@ __device__ __forceinline__ void stage1d_tile(const StageArgs& a, const Tile tile
     for (int c = 0; c < M; ++c) {
       R L;
       if constexpr (kExact)
-        L = -(s_F[c][tid] - s_F[c][tid - 1]) / dx;
+        L = -div_rn(s_F[c][tid] - s_F[c][tid - 1], dx);
       else
         L = (s_F[c][tid - 1] - s_F[c][tid]) * inv_dx;
       if (stage == 0) {
@@ -294,7 +303,7 @@ __device__ __forceinline__ void stage1d_tile(const StageArgs& a, const Tile tile
 
 // Grid-stride loop over the tile table; the tile count is read from device memory when the
 // table is shared with a serving loop, so captured graphs stay valid as instances come and go.
-template <typename R, int FLUX, int M, int BS>
+template <typename R, int FLUX, int M, int BS, bool CHAR = false>
 __global__ __launch_bounds__(BS) void stage1d_kernel(StageArgs a) {
   if (a.tiles == nullptr) {  // single instance: tiles follow from the block index
     Tile t;
@@ -303,12 +312,12 @@ __global__ __launch_bounds__(BS) void stage1d_kernel(StageArgs a) {
     t.start = (long long)blockIdx.x * (BS - 2);
     t.nx = a.nx;
     t.off = 0;
-    stage1d_tile<R, FLUX, M, BS>(a, t);
+    stage1d_tile<R, FLUX, M, BS, CHAR>(a, t);
     return;
   }
   const int nt = a.ntiles_dev ? *a.ntiles_dev : a.ntiles;
   for (int ti = blockIdx.x; ti < nt; ti += gridDim.x) {
-    stage1d_tile<R, FLUX, M, BS>(a, a.tiles[ti]);
+    stage1d_tile<R, FLUX, M, BS, CHAR>(a, a.tiles[ti]);
     __syncthreads();  // LDS is reused by the next tile
   }
 }

@@ -15,7 +15,7 @@
 
 namespace npw {
 
-template <typename R, int FLUX, int M, int TX, int TY>
+template <typename R, int FLUX, int M, int TX, int TY, bool CHAR = false>
 __global__ __launch_bounds__(256) void stage2d_kernel(StageArgs a) {
   constexpr int BS = 256;
   constexpr bool kExact = std::is_same<R, double>::value;
@@ -169,15 +169,16 @@ __global__ __launch_bounds__(256) void stage2d_kernel(StageArgs a) {
     constexpr int NPOS = LEN + 2;  // cells -1 .. LEN
     auto U = [&](int c, int line, int q) -> R { return DIR == 0 ? s_u[c][line + 3][q] : s_u[c][q][line + 3]; };
     auto cid = [&](int line, int pos) -> int { return DIR == 0 ? line * NPOS + pos + 1 : (pos + 1) * LINES + line; };
-    // cell phase: flag and weight denominators of cells -1..LEN of every line
-    for (int w = tid; w < NPOS * LINES; w += BS) {
+    // cell phase: flag and weight denominators of cells -1..LEN of every line (none in the
+    // characteristic mode: its fields belong to an interface)
+    for (int w = tid; w < (CHAR ? 0 : NPOS * LINES); w += BS) {
       const int line = DIR == 0 ? w / NPOS : w % LINES;
       const int pos = DIR == 0 ? w % NPOS - 1 : w / LINES - 1;
       const int q = pos + 3;
 #pragma unroll
       for (int c = 0; c < M; ++c) {
         // bit 0: switch flag; bits 1-2: ENO stencil
-        int fl = use_switch ? monotone_flag(double(U(c, line, q - 1)), double(U(c, line, q)),
+        int fl = use_switch ? monotone_flag<kExact>(double(U(c, line, q - 1)), double(U(c, line, q)),
                                             double(U(c, line, q + 1)))
                             : 0;
         if (k2) {  // k = 2: ENO2 stencil and the right/left edge shape parameters of the cell
@@ -185,8 +186,8 @@ __global__ __launch_bounds__(256) void stage2d_kernel(StageArgs a) {
           if (eno) fl |= eno2_stencil(um, u0, up) << 1;
           double er = 0.0, el = 0.0;
           if (use_eta && !(fl & 1)) {
-            er = eta2_ratio(um, u0, up, eps_m);
-            el = eta2_ratio(up, u0, um, eps_m);
+            er = eta2_ratio<kExact>(um, u0, up, eps_m);
+            el = eta2_ratio<kExact>(up, u0, um, eps_m);
           }
           s_den[c][0][w] = R(er);
           s_den[c][1][w] = R(el);
@@ -213,8 +214,16 @@ __global__ __launch_bounds__(256) void stage2d_kernel(StageArgs a) {
       const int q = pos + 3;
       const int wl = cid(line, pos), wr = cid(line, pos + 1);
       R A[M], B[M], H[M];
+      if constexpr (CHAR) {  // cells pos-2..pos+3 along the sweep
+        R Uw[6][M];
 #pragma unroll
-      for (int c = 0; c < M; ++c) {
+        for (int k = 0; k < 6; ++k)
+#pragma unroll
+          for (int c = 0; c < M; ++c) Uw[k][c] = U(c, line, q - 2 + k);
+        char_states<R, M, DIR>(Uw, gamma, rm, eps, eps_m, A, B);
+      }
+#pragma unroll
+      for (int c = 0; c < (CHAR ? 0 : M); ++c) {
         if (k2) {
           const R el = s_den[c][0][wl], er = s_den[c][1][wr];
           if (eno) {
@@ -228,7 +237,7 @@ __global__ __launch_bounds__(256) void stage2d_kernel(StageArgs a) {
         }
         double e = 0.0;
         if (use_eta) {
-          e = eta_ratio(double(U(c, line, q - 1)), double(U(c, line, q)), double(U(c, line, q + 1)),
+          e = eta_ratio<kExact>(double(U(c, line, q - 1)), double(U(c, line, q)), double(U(c, line, q + 1)),
                         double(U(c, line, q + 2)), eps_m);
           if (use_switch && ((s_flag[c][wl] | s_flag[c][wr]) & 1)) e = 0.0;
         }
@@ -263,12 +272,12 @@ __global__ __launch_bounds__(256) void stage2d_kernel(StageArgs a) {
         const R Fp = s_F[c][wp], Fm = s_F[c][wm];
         if constexpr (DIR == 0) {
           if constexpr (kExact)
-            s_L[c][y][x] = -(Fp - Fm) / dx;
+            s_L[c][y][x] = -div_rn(Fp - Fm, dx);
           else
             s_L[c][y][x] = (Fm - Fp) * inv_dx;
         } else {
           if constexpr (kExact)
-            s_L[c][y][x] = s_L[c][y][x] - (Fp - Fm) / dy;
+            s_L[c][y][x] = s_L[c][y][x] - div_rn(Fp - Fm, dy);
           else
             s_L[c][y][x] = s_L[c][y][x] + (Fm - Fp) * inv_dy;
         }

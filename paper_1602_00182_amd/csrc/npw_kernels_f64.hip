@@ -12,6 +12,8 @@ static hipError_t launch_stage_bs(int flux, int ncomp, const StageArgs& a, hipSt
     stage1d_kernel<double, kAdvection, 1, BS><<<grid, block, 0, s>>>(a);
   else if (flux == kBurgers && ncomp == 1)
     stage1d_kernel<double, kBurgers, 1, BS><<<grid, block, 0, s>>>(a);
+  else if (flux == kEuler && ncomp == 3 && a.charw)
+    stage1d_kernel<double, kEuler, 3, BS, true><<<grid, block, 0, s>>>(a);
   else if (flux == kEuler && ncomp == 3)
     stage1d_kernel<double, kEuler, 3, BS><<<grid, block, 0, s>>>(a);
   else
@@ -32,7 +34,9 @@ hipError_t launch_stage_f64(int flux, int ncomp, int block, const StageArgs& a, 
 template <int TX, int TY>
 static hipError_t launch2d(int flux, int ncomp, const StageArgs& a, hipStream_t s) {
   const dim3 grid((unsigned)((a.nx + TX - 1) / TX), (unsigned)((a.ny + TY - 1) / TY)), block(256);
-  if (flux == kEuler && ncomp == 4)
+  if (flux == kEuler && ncomp == 4 && a.charw)
+    stage2d_kernel<double, kEuler, 4, TX, TY, true><<<grid, block, 0, s>>>(a);
+  else if (flux == kEuler && ncomp == 4)
     stage2d_kernel<double, kEuler, 4, TX, TY><<<grid, block, 0, s>>>(a);
   else if (flux == kAdvection && ncomp == 1)
     stage2d_kernel<double, kAdvection, 1, TX, TY><<<grid, block, 0, s>>>(a);

@@ -26,6 +26,7 @@ using npw::Tile;
 
 struct npw_solver {
   int precision = NPW_FP64, flux = 0, ncomp = 1, dim = 1;
+  int charw = 0;                // characteristic-wise Euler reconstruction (all instances)
   size_t esize = 8;
   int ninst = 0;
   int block = 256;              // 1D stage workgroup size (tile = block - 2 cells)
@@ -89,6 +90,9 @@ int validate(const npw_params* p) {
   if (!finite_pos(p->cfl) || !finite_pos(p->eps_weno) || !finite_pos(p->eps_m)) return NPW_EINVAL;
   if (!(std::isfinite(p->dt_fixed) && p->dt_fixed >= 0.0)) return NPW_EINVAL;
   if (!std::isfinite(p->speed_x) || !std::isfinite(p->speed_y)) return NPW_EINVAL;
+  if (p->variables != NPW_COMPONENTWISE && (p->variables != NPW_CHARACTERISTIC || p->flux != NPW_EULER))
+    return NPW_EINVAL;
+  if (p->reserved != 0) return NPW_EINVAL;
   return NPW_OK;
 }
 
@@ -129,6 +133,7 @@ StageArgs stage_args(const npw_solver* s, int stage, int par, void* out) {
   a.C = s->C;
   a.out = out;
   a.stage = stage;
+  a.charw = s->charw;
   a.spread = s->spread;
   return a;
 }
@@ -302,7 +307,7 @@ std::string tune_key(const npw_solver* s) {
   while ((1ll << (lg + 1)) <= cells) ++lg;
   std::ostringstream k;
   k << "v1_d" << s->dim << "_f" << s->flux << "_m" << s->ncomp << "_p" << s->precision << "_n" << lg << "_i"
-    << (s->ninst > 1 ? 1 : 0);
+    << (s->ninst > 1 ? 1 : 0) << (s->charw ? "_c" : "");
   return k.str();
 }
 
@@ -535,6 +540,8 @@ void npweno_default_params(npw_params* p) {
   p->eps_weno = 1e-6;
   p->eps_m = 1e-12;
   p->dt_fixed = 0.0;
+  p->variables = NPW_COMPONENTWISE;
+  p->reserved = 0;
 }
 
 // Build a solver for `count` instances sharing precision, flux and dimension.  u0[b] holds the
@@ -550,7 +557,7 @@ static int create_common(const npw_params* p, int32_t count, const void* const* 
     if (batch && p[b].dim != 1) return NPW_EINVAL;  // batches are 1D
     if (!u0[b]) return NPW_EINVAL;
     if (p[b].precision != p[0].precision || p[b].flux != p[0].flux || p[b].ncomp != p[0].ncomp ||
-        p[b].dim != p[0].dim)
+        p[b].dim != p[0].dim || p[b].variables != p[0].variables)
       return NPW_EINVAL;
   }
   npw_solver* s = new (std::nothrow) npw_solver();
@@ -559,6 +566,7 @@ static int create_common(const npw_params* p, int32_t count, const void* const* 
   s->flux = p[0].flux;
   s->ncomp = p[0].ncomp;
   s->dim = p[0].dim;
+  s->charw = p[0].variables == NPW_CHARACTERISTIC ? 1 : 0;
   s->esize = p[0].precision == NPW_FP64 ? sizeof(double) : sizeof(float);
   s->ninst = count;
   s->batch = batch;

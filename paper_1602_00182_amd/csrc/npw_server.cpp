@@ -50,6 +50,7 @@ struct Request {
 
 struct Pool {
   int flux = 0, ncomp = 1;
+  int charw = 0;              // Euler characteristic-wise reconstruction
   hipStream_t stream = nullptr;
   InstDev* d_inst = nullptr;
   InstDev* h_pin = nullptr;
@@ -118,7 +119,7 @@ struct npw_server {
   void* P1 = nullptr;
   void* C = nullptr;
   Arena arena;
-  Pool pools[3];
+  Pool pools[4];  // advection, Burgers, Euler, Euler (characteristic-wise)
   std::deque<size_t> queue;       // indices into reqs (FIFO)
   std::vector<Request> reqs;      // every request ever submitted (by index)
   std::map<uint64_t, size_t> index;
@@ -134,7 +135,9 @@ namespace {
     if (e_ != hipSuccess) return NPW_EHIP; \
   } while (0)
 
-int pool_of(const npw_params* p) { return p->flux; }  // advection 0, Burgers 1, Euler 2
+int pool_of(const npw_params* p) {  // advection 0, Burgers 1, Euler 2, Euler characteristic-wise 3
+  return p->flux == NPW_EULER && p->variables == NPW_CHARACTERISTIC ? 3 : p->flux;
+}
 
 hipError_t launch_stage(const npw_server* s, int flux, int ncomp, const StageArgs& a, hipStream_t st) {
   return s->precision == NPW_FP64 ? npw::launch_stage_f64(flux, ncomp, kBlock, a, st)
@@ -154,6 +157,7 @@ StageArgs pool_args(const npw_server* s, const Pool& pl, int stage, int par) {
   a.C = s->C;
   a.stage = stage;
   a.spread = nullptr;
+  a.charw = pl.charw;
   return a;
 }
 
@@ -220,6 +224,9 @@ int validate_request(const npw_server* s, const npw_params* p) {
   if (!(p->cfl > 0.0) || !(p->eps_weno > 0.0) || !(p->eps_m > 0.0) || !(p->dt_fixed >= 0.0)) return NPW_EINVAL;
   if (!std::isfinite(p->cfl) || !std::isfinite(p->eps_weno) || !std::isfinite(p->eps_m)) return NPW_EINVAL;
   if (!std::isfinite(p->speed_x)) return NPW_EINVAL;
+  if (p->variables != NPW_COMPONENTWISE && (p->variables != NPW_CHARACTERISTIC || p->flux != NPW_EULER))
+    return NPW_EINVAL;
+  if (p->reserved != 0) return NPW_EINVAL;
   return NPW_OK;
 }
 
@@ -382,11 +389,12 @@ int npw_server_create(size_t hbm_budget_bytes, int32_t max_slots, int32_t precis
   bool ok = hipMalloc(&s->P0, elems * esize) == hipSuccess && hipMalloc(&s->P1, elems * esize) == hipSuccess &&
             hipMalloc(&s->C, elems * esize) == hipSuccess &&
             hipEventCreateWithFlags(&s->ev, hipEventDisableTiming) == hipSuccess;
-  const int ncomp[3] = {1, 1, 3};
-  for (int k = 0; k < 3 && ok; ++k) {
+  const int ncomp[4] = {1, 1, 3, 3};
+  for (int k = 0; k < 4 && ok; ++k) {
     Pool& pl = s->pools[k];
-    pl.flux = k;
+    pl.flux = k < 3 ? k : NPW_EULER;
     pl.ncomp = ncomp[k];
+    pl.charw = k == 3 ? 1 : 0;
     pl.slot_req.assign(max_slots, -1);
     pl.slot_id.assign(max_slots, 0);
     // every tile of a full arena (one component per element) plus one partial tile per slot

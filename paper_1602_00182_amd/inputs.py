@@ -29,6 +29,7 @@ PERIODIC, TRANSMISSIVE = 0, 1
 RBF_WENO5, WENO5_JS, RBF_ENO3, ENO3 = 0, 1, 2, 3  # k = 3 (Table 3)
 RBF_WENO3, WENO3_JS, RBF_ENO2, ENO2 = 4, 5, 6, 7  # k = 2 (Table 2)
 SWITCH_MONOTONE, SWITCH_OFF = 0, 1
+COMPONENTWISE, CHARACTERISTIC = 0, 1
 
 
 @dataclass
@@ -56,6 +57,7 @@ class Workload:
     recon: int = RBF_WENO5
     switch_mode: int = SWITCH_MONOTONE
     dt_fixed: float = 0.0
+    variables: int = COMPONENTWISE
     meta: dict = field(default_factory=dict)
 
     @property
@@ -69,7 +71,7 @@ class Workload:
     def params(self) -> dict:
         """Problem parameters as plain keyword values (no initial data)."""
         keys = ("dim", "flux", "ncomp", "nx", "ny", "x0", "x1", "y0", "y1", "bc", "speed_x", "speed_y",
-                "gamma", "cfl", "eps_weno", "eps_m", "recon", "switch_mode", "dt_fixed")
+                "gamma", "cfl", "eps_weno", "eps_m", "recon", "switch_mode", "dt_fixed", "variables")
         return {k: getattr(self, k) for k in keys}
 
     def with_(self, **kw) -> "Workload":

@@ -47,15 +47,17 @@ def test_abi_version_and_strerror(L):
 def test_params_struct_matches_header_defaults(L):
     from paper_1602_00182_amd import binding as B
     p = B.make_params()
-    assert p.abi_version == 1 and p.dim == 1 and p.nx == 80 and p.eps_m == 1e-12 and p.eps_weno == 1e-6
-    assert ctypes.sizeof(B.Params) == 8 * 4 + 8 * 2 + 8 * 11
+    assert p.abi_version == 2 and p.dim == 1 and p.nx == 80 and p.eps_m == 1e-12 and p.eps_weno == 1e-6
+    assert p.variables == B.COMPONENTWISE and p.reserved == 0
+    assert ctypes.sizeof(B.Params) == 8 * 4 + 8 * 2 + 8 * 11 + 8
 
 
 @pytest.mark.parametrize("bad", [
     {"nx": 0}, {"flux": 7}, {"flux": 2, "ncomp": 1}, {"ncomp": 3}, {"bc": 5}, {"precision": 3},
     {"cfl": 0.0}, {"cfl": float("nan")}, {"eps_weno": -1.0}, {"eps_m": 0.0}, {"x1": -2.0},
     {"abi_version": 99}, {"recon": 8}, {"switch_mode": 9}, {"dt_fixed": -1.0},
-    {"flux": 2, "ncomp": 3, "gamma": 1.0},
+    {"flux": 2, "ncomp": 3, "gamma": 1.0}, {"variables": 1}, {"flux": 2, "ncomp": 3, "variables": 2},
+    {"reserved": 1},
 ])
 def test_create_rejects_bad_parameters_before_allocating(L, bad):
     from paper_1602_00182_amd import binding as B
