@@ -133,7 +133,8 @@ def bench_single(args, w, prec):
     if w.dim == 1:
         label = f"stage1d_kernel<{R}, Burgers, 1, {shape['block']}>"
     else:
-        label = f"stage2d_kernel<{R}, Euler, 4, {shape['tile_x']}, {shape['tile_y']}>"
+        share = "" if shape["lds_shared"] else ", recompute"
+        label = f"stage2d_kernel<{R}, Euler, 4, {shape['tile_x']}, {shape['tile_y']}{share}>"
     wall, gpu_s, lat, rk = _time_solves(solver, lambda: solver.write(u0_dev, 0.0), w.T, args.steps, args.warmup,
                                         args.max_rk_steps, stream)
     ncell = w.ncell

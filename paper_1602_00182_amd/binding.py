@@ -95,7 +95,7 @@ def lib():
         L.npweno_instance_count.argtypes = [_VP]
         L.npweno_instance_count.restype = ctypes.c_int
         I32P = ctypes.POINTER(ctypes.c_int32)
-        L.npweno_launch_shape.argtypes = [_VP, I32P, I32P, I32P]
+        L.npweno_launch_shape.argtypes = [_VP, I32P, I32P, I32P, I32P]
         U64 = ctypes.c_uint64
         L.npw_server_create.argtypes = [ctypes.c_size_t, ctypes.c_int32, ctypes.c_int32, _VP, ctypes.POINTER(_VP)]
         L.npw_server_submit.argtypes = [_VP, P, _VP, ctypes.c_double, ctypes.POINTER(U64)]
@@ -213,10 +213,10 @@ class Solver:
 
     def launch_shape(self) -> dict:
         """Stage-kernel launch shape in use: 1D threads per workgroup, 2D owned tile."""
-        b, tx, ty = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
-        _check(lib().npweno_launch_shape(self.h, ctypes.byref(b), ctypes.byref(tx), ctypes.byref(ty)),
-               "npweno_launch_shape")
-        return {"block": b.value, "tile_x": tx.value, "tile_y": ty.value}
+        b, tx, ty, sh = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().npweno_launch_shape(self.h, ctypes.byref(b), ctypes.byref(tx), ctypes.byref(ty),
+                                         ctypes.byref(sh)), "npweno_launch_shape")
+        return {"block": b.value, "tile_x": tx.value, "tile_y": ty.value, "lds_shared": sh.value}
 
     def close(self):
         if getattr(self, "h", None):

@@ -46,6 +46,17 @@ __device__ __forceinline__ double div_rn(double a, double b) {
   if (e1 < e0 || (e1 == e0 && (nb & 1) == 0)) return q1;
   return q;
 }
+// Faithful double quotient (error below one unit in the last place) for normal operands: the
+// hardware reciprocal, two Newton steps and one residual correction.  Used by the float bulk path
+// for double ratios that are rounded to float afterwards.
+__device__ __forceinline__ double div_faithful(double a, double b) {
+  double r = __builtin_amdgcn_rcp(b);
+  r = fma(fma(-b, r, 1.0), r, r);
+  r = fma(fma(-b, r, 1.0), r, r);
+  const double q = a * r;
+  return fma(fma(-b, q, a), r, q);
+}
+
 // Division in the bulk precision: correctly rounded in double (the exact flavour), the plain
 // operator in float.
 template <typename R>
@@ -61,14 +72,23 @@ __device__ __forceinline__ R fdiv(R a, R b) {
 // x_p/dx = (-2u_{j-1} + 3u_j - u_{j+1}) / (-u_{j-1} + 2u_j - u_{j+1}) from x_{j-3/2}; the window is
 // not monotone when 0 < x_p/dx < 3.  Division by zero (linear data) gives inf/NaN, which fails
 // the strict test.  Double precision, uncontracted: the decision is the one the quotient makes.
-// CR: correctly rounded quotient (double bulk); otherwise the hardware quotient.
+// CR (double bulk): the test on the correctly rounded quotient, as written.  Otherwise (float
+// bulk: the window holds float values, so num and den are exact in double and 3 den is too) the
+// same decision without the quotient: 0 < num/den < 3 holds exactly when num and den are non-zero
+// with one sign and num lies on the near side of 3 den.  A quotient of such operands cannot lie
+// within rounding distance of 0 or 3 without equalling it, so both forms decide alike.
 template <bool CR = true>
 __device__ __forceinline__ int monotone_flag(double um1, double u0, double up1) {
 #pragma clang fp contract(off)
   double num = -2.0 * um1 + 3.0 * u0 - up1;
   double den = -um1 + 2.0 * u0 - up1;
-  double xp = CR ? div_rn(num, den) : num / den;
-  return (xp > 0.0 && xp < 3.0) ? 1 : 0;
+  if constexpr (CR) {
+    double xp = div_rn(num, den);
+    return (xp > 0.0 && xp < 3.0) ? 1 : 0;
+  } else {
+    if (num == 0.0 || den == 0.0 || (num > 0.0) != (den > 0.0)) return 0;
+    return (den > 0.0 ? num < 3.0 * den : num > 3.0 * den) ? 1 : 0;
+  }
 }
 
 // Shape parameter eta = eps^2 dx^2 at x_{i+1/2} (Table 3 caption) from u_{i-1}..u_{i+2}:
@@ -83,7 +103,7 @@ __device__ __forceinline__ double eta_ratio(double um1, double u0, double up1, d
     den = den + eps_m;
   else
     den = den - eps_m;
-  return CR ? div_rn(num, den) : num / den;
+  return CR ? div_rn(num, den) : div_faithful(num, den);
 }
 
 // Jiang-Shu smoothness indicators of cell i from (a..e) = u_{i-2}..u_{i+2}; b0 for the stencil
@@ -283,7 +303,7 @@ __device__ __forceinline__ double eta2_ratio(double ufar, double u0, double unea
     den = den + eps_m;
   else
     den = den - eps_m;
-  return CR ? div_rn(num, den) : num / den;
+  return CR ? div_rn(num, den) : div_faithful(num, den);
 }
 
 // WENO3 edge values of cell i from (a, b, c) = u_{i-1}, u_i, u_{i+1}: v^-_{i+1/2} combines row 0 on

@@ -67,6 +67,7 @@ struct StageArgs {
   void* out; // rhs mode: destination of L(u)
   int stage; // 1, 2, 3: SSP-RK3 stage; 0: evaluate L(u^n) into out
   int charw; // Euler: 1 = characteristic-wise reconstruction (same for every instance of a launch)
+  int any_k2; // some instance of the launch uses a k = 2 reconstruction (0 prunes that code)
   // Single-grid solvers spread each alpha slot over kSpread cache lines so that hundreds of
   // workgroups do not queue on one atomic: entry (slot, dir, k) lives at
   // spread[((slot * 2 + dir) * kSpread + k) * kSpreadStride].  Null for batches (they use
@@ -82,8 +83,9 @@ constexpr int kSpreadWords = 3 * 2 * kSpread * kSpreadStride;
 hipError_t launch_stage_f64(int flux, int ncomp, int block, const StageArgs& a, hipStream_t s);
 hipError_t launch_stage_f32(int flux, int ncomp, int block, const StageArgs& a, hipStream_t s);
 // Recompute alpha slot 0, finiteness/physicality checks and the per-component sums of u^n.
-// 2D tile shapes: 0 = 64 x 8, 1 = 62 x 8, 2 = 126 x 4 cells.
-constexpr int k2dShapes = 3;
+// 2D launch shapes: tiles 0 = 64 x 8, 1 = 62 x 8, 2 = 126 x 4 cells with per-cell values shared
+// through LDS; 3, 4, 5 = the same tiles with those values recomputed per interface.
+constexpr int k2dShapes = 6;
 hipError_t launch_stage2d_f64(int flux, int ncomp, int shape, const StageArgs& a, hipStream_t s);
 hipError_t launch_stage2d_f32(int flux, int ncomp, int shape, const StageArgs& a, hipStream_t s);
 // scratch holds G * ninst partial records (kCheckPartialBytes each); G workgroups per instance.

@@ -21,7 +21,7 @@
 
 namespace npw {
 
-template <typename R, int FLUX, int M, int BS, bool CHAR>
+template <typename R, int FLUX, int M, int BS, bool CHAR, bool K2>
 __device__ __forceinline__ void stage1d_tile(const StageArgs& a, const Tile tile) {
   constexpr bool kExact = std::is_same<R, double>::value;
   constexpr int W = BS + 4;  // LDS cells per component: start-3 .. start+BS
@@ -134,7 +134,8 @@ __device__ __forceinline__ void stage1d_tile(const StageArgs& a, const Tile tile
   }
   const R alpha = R(bits_to_double(alpha_bits));
   const R rdt = R(dt);
-  const ReconMode rm = recon_mode(I->recon, I->sw);
+  ReconMode rm = recon_mode(I->recon, I->sw);
+  if (!K2) rm.k2 = false;  // launched for k = 3 instances only
   const bool k2 = rm.k2, eno = rm.eno, use_eta = rm.use_eta, use_switch = rm.use_switch;
   const double eps_m = I->eps_m;
   const R eps = R(I->eps_weno);
@@ -303,7 +304,7 @@ __device__ __forceinline__ void stage1d_tile(const StageArgs& a, const Tile tile
 
 // Grid-stride loop over the tile table; the tile count is read from device memory when the
 // table is shared with a serving loop, so captured graphs stay valid as instances come and go.
-template <typename R, int FLUX, int M, int BS, bool CHAR = false>
+template <typename R, int FLUX, int M, int BS, bool CHAR = false, bool K2 = true>
 __global__ __launch_bounds__(BS) void stage1d_kernel(StageArgs a) {
   if (a.tiles == nullptr) {  // single instance: tiles follow from the block index
     Tile t;
@@ -312,12 +313,12 @@ __global__ __launch_bounds__(BS) void stage1d_kernel(StageArgs a) {
     t.start = (long long)blockIdx.x * (BS - 2);
     t.nx = a.nx;
     t.off = 0;
-    stage1d_tile<R, FLUX, M, BS, CHAR>(a, t);
+    stage1d_tile<R, FLUX, M, BS, CHAR, K2>(a, t);
     return;
   }
   const int nt = a.ntiles_dev ? *a.ntiles_dev : a.ntiles;
   for (int ti = blockIdx.x; ti < nt; ti += gridDim.x) {
-    stage1d_tile<R, FLUX, M, BS, CHAR>(a, a.tiles[ti]);
+    stage1d_tile<R, FLUX, M, BS, CHAR, K2>(a, a.tiles[ti]);
     __syncthreads();  // LDS is reused by the next tile
   }
 }

@@ -15,7 +15,10 @@
 
 namespace npw {
 
-template <typename R, int FLUX, int M, int TX, int TY, bool CHAR = false>
+// SHARE: the per-cell weight denominators and k = 2 shape parameters go through LDS and serve both
+// interfaces of a cell; otherwise every interface recomputes them (less LDS, more workgroups per
+// compute unit).  The switch flags and ENO stencils are shared either way.
+template <typename R, int FLUX, int M, int TX, int TY, bool CHAR = false, bool K2 = true, bool SHARE = true>
 __global__ __launch_bounds__(256) void stage2d_kernel(StageArgs a) {
   constexpr int BS = 256;
   constexpr bool kExact = std::is_same<R, double>::value;
@@ -23,7 +26,7 @@ __global__ __launch_bounds__(256) void stage2d_kernel(StageArgs a) {
   constexpr int NC = (TX + 2) * TY > TX * (TY + 2) ? (TX + 2) * TY : TX * (TY + 2);  // sweep cells
   __shared__ R s_u[M][WY][WX];
   __shared__ unsigned char s_flag[M][NC];
-  __shared__ R s_den[M][3][NC];
+  __shared__ R s_den[SHARE ? M : 1][3][SHARE ? NC : 1];
   __shared__ R s_F[M][NC];
   __shared__ R s_L[M][TY][TX];
   static_assert(TX % 1 == 0 && TY % 1 == 0 && NC >= (TX + 2) * TY, "sweep buffers");
@@ -140,7 +143,8 @@ __global__ __launch_bounds__(256) void stage2d_kernel(StageArgs a) {
   }
   const R alpha_x = R(bits_to_double(ax_bits)), alpha_y = R(bits_to_double(ay_bits));
   const R rdt = R(dt);
-  const ReconMode rm = recon_mode(I->recon, I->sw);
+  ReconMode rm = recon_mode(I->recon, I->sw);
+  if (!K2) rm.k2 = false;  // launched for a k = 3 instance
   const bool k2 = rm.k2, eno = rm.eno, use_eta = rm.use_eta, use_switch = rm.use_switch;
   const double eps_m = I->eps_m;
   const R eps = R(I->eps_weno);
@@ -184,18 +188,20 @@ __global__ __launch_bounds__(256) void stage2d_kernel(StageArgs a) {
         if (k2) {  // k = 2: ENO2 stencil and the right/left edge shape parameters of the cell
           const double um = double(U(c, line, q - 1)), u0 = double(U(c, line, q)), up = double(U(c, line, q + 1));
           if (eno) fl |= eno2_stencil(um, u0, up) << 1;
-          double er = 0.0, el = 0.0;
-          if (use_eta && !(fl & 1)) {
-            er = eta2_ratio<kExact>(um, u0, up, eps_m);
-            el = eta2_ratio<kExact>(up, u0, um, eps_m);
+          if constexpr (SHARE) {
+            double er = 0.0, el = 0.0;
+            if (use_eta && !(fl & 1)) {
+              er = eta2_ratio<kExact>(um, u0, up, eps_m);
+              el = eta2_ratio<kExact>(up, u0, um, eps_m);
+            }
+            s_den[c][0][w] = R(er);
+            s_den[c][1][w] = R(el);
           }
-          s_den[c][0][w] = R(er);
-          s_den[c][1][w] = R(el);
         } else if (eno) {
           fl |= eno_stencil(double(U(c, line, q - 2)), double(U(c, line, q - 1)), double(U(c, line, q)),
                             double(U(c, line, q + 1)), double(U(c, line, q + 2)))
                 << 1;
-        } else {
+        } else if constexpr (SHARE) {
           R d0, d1, d2;
           weight_denominators<R>(U(c, line, q - 2), U(c, line, q - 1), U(c, line, q), U(c, line, q + 1),
                                  U(c, line, q + 2), eps, d0, d1, d2);
@@ -225,7 +231,21 @@ __global__ __launch_bounds__(256) void stage2d_kernel(StageArgs a) {
 #pragma unroll
       for (int c = 0; c < (CHAR ? 0 : M); ++c) {
         if (k2) {
-          const R el = s_den[c][0][wl], er = s_den[c][1][wr];
+          R el, er;
+          if constexpr (SHARE) {
+            el = s_den[c][0][wl];
+            er = s_den[c][1][wr];
+          } else {  // right-edge parameter of the left cell, left-edge parameter of the right cell
+            double dl = 0.0, dr = 0.0;
+            if (use_eta && !(s_flag[c][wl] & 1))
+              dl = eta2_ratio<kExact>(double(U(c, line, q - 1)), double(U(c, line, q)), double(U(c, line, q + 1)),
+                                      eps_m);
+            if (use_eta && !(s_flag[c][wr] & 1))
+              dr = eta2_ratio<kExact>(double(U(c, line, q + 2)), double(U(c, line, q + 1)), double(U(c, line, q)),
+                                      eps_m);
+            el = R(dl);
+            er = R(dr);
+          }
           if (eno) {
             A[c] = eno2<R, false>((s_flag[c][wl] >> 1) & 1, U(c, line, q - 1), U(c, line, q), U(c, line, q + 1), el);
             B[c] = eno2<R, true>((s_flag[c][wr] >> 1) & 1, U(c, line, q), U(c, line, q + 1), U(c, line, q + 2), er);
@@ -247,11 +267,19 @@ __global__ __launch_bounds__(256) void stage2d_kernel(StageArgs a) {
                               U(c, line, q + 1), U(c, line, q + 2), eta);
           B[c] = eno_plus<R>(s_flag[c][wr] >> 1, U(c, line, q - 1), U(c, line, q), U(c, line, q + 1),
                              U(c, line, q + 2), U(c, line, q + 3), eta);
-        } else {
+        } else if constexpr (SHARE) {
           A[c] = weno_minus<R>(U(c, line, q - 2), U(c, line, q - 1), U(c, line, q), U(c, line, q + 1),
                                U(c, line, q + 2), eta, s_den[c][0][wl], s_den[c][1][wl], s_den[c][2][wl]);
           B[c] = weno_plus<R>(U(c, line, q - 1), U(c, line, q), U(c, line, q + 1), U(c, line, q + 2),
                               U(c, line, q + 3), eta, s_den[c][0][wr], s_den[c][1][wr], s_den[c][2][wr]);
+        } else {
+          const R u0 = U(c, line, q - 2), u1 = U(c, line, q - 1), u2 = U(c, line, q), u3 = U(c, line, q + 1),
+                  u4 = U(c, line, q + 2), u5 = U(c, line, q + 3);
+          R d0, d1, d2;
+          weight_denominators<R>(u0, u1, u2, u3, u4, eps, d0, d1, d2);
+          A[c] = weno_minus<R>(u0, u1, u2, u3, u4, eta, d0, d1, d2);
+          weight_denominators<R>(u1, u2, u3, u4, u5, eps, d0, d1, d2);
+          B[c] = weno_plus<R>(u1, u2, u3, u4, u5, eta, d0, d1, d2);
         }
       }
       if constexpr (DIR == 0)

@@ -4,21 +4,26 @@
 
 namespace npw {
 
-template <int BS>
-static hipError_t launch_stage_bs(int flux, int ncomp, const StageArgs& a, hipStream_t s) {
-  if (a.ntiles <= 0) return hipSuccess;
+template <int BS, bool K2>
+static hipError_t launch_stage_k(int flux, int ncomp, const StageArgs& a, hipStream_t s) {
   const dim3 grid(a.ntiles), block(BS);
   if (flux == kAdvection && ncomp == 1)
-    stage1d_kernel<double, kAdvection, 1, BS><<<grid, block, 0, s>>>(a);
+    stage1d_kernel<double, kAdvection, 1, BS, false, K2><<<grid, block, 0, s>>>(a);
   else if (flux == kBurgers && ncomp == 1)
-    stage1d_kernel<double, kBurgers, 1, BS><<<grid, block, 0, s>>>(a);
+    stage1d_kernel<double, kBurgers, 1, BS, false, K2><<<grid, block, 0, s>>>(a);
   else if (flux == kEuler && ncomp == 3 && a.charw)
-    stage1d_kernel<double, kEuler, 3, BS, true><<<grid, block, 0, s>>>(a);
+    stage1d_kernel<double, kEuler, 3, BS, true, K2><<<grid, block, 0, s>>>(a);
   else if (flux == kEuler && ncomp == 3)
-    stage1d_kernel<double, kEuler, 3, BS><<<grid, block, 0, s>>>(a);
+    stage1d_kernel<double, kEuler, 3, BS, false, K2><<<grid, block, 0, s>>>(a);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();
+}
+
+template <int BS>
+static hipError_t launch_stage_bs(int flux, int ncomp, const StageArgs& a, hipStream_t s) {
+  if (a.ntiles <= 0) return hipSuccess;
+  return a.any_k2 ? launch_stage_k<BS, true>(flux, ncomp, a, s) : launch_stage_k<BS, false>(flux, ncomp, a, s);
 }
 
 hipError_t launch_stage_f64(int flux, int ncomp, int block, const StageArgs& a, hipStream_t s) {
@@ -30,28 +35,38 @@ hipError_t launch_stage_f64(int flux, int ncomp, int block, const StageArgs& a, 
   }
 }
 
-// 2D tiles (x contiguous), one workgroup of 256 threads each; the shape is tunable.
-template <int TX, int TY>
-static hipError_t launch2d(int flux, int ncomp, const StageArgs& a, hipStream_t s) {
+// 2D stage launch for one tile shape, with or without the k = 2 code.
+template <int TX, int TY, bool K2, bool SHARE>
+static hipError_t launch2d_k(int flux, int ncomp, const StageArgs& a, hipStream_t s) {
   const dim3 grid((unsigned)((a.nx + TX - 1) / TX), (unsigned)((a.ny + TY - 1) / TY)), block(256);
   if (flux == kEuler && ncomp == 4 && a.charw)
-    stage2d_kernel<double, kEuler, 4, TX, TY, true><<<grid, block, 0, s>>>(a);
+    stage2d_kernel<double, kEuler, 4, TX, TY, true, K2><<<grid, block, 0, s>>>(a);
   else if (flux == kEuler && ncomp == 4)
-    stage2d_kernel<double, kEuler, 4, TX, TY><<<grid, block, 0, s>>>(a);
+    stage2d_kernel<double, kEuler, 4, TX, TY, false, K2, SHARE><<<grid, block, 0, s>>>(a);
   else if (flux == kAdvection && ncomp == 1)
-    stage2d_kernel<double, kAdvection, 1, TX, TY><<<grid, block, 0, s>>>(a);
+    stage2d_kernel<double, kAdvection, 1, TX, TY, false, K2, SHARE><<<grid, block, 0, s>>>(a);
   else if (flux == kBurgers && ncomp == 1)
-    stage2d_kernel<double, kBurgers, 1, TX, TY><<<grid, block, 0, s>>>(a);
+    stage2d_kernel<double, kBurgers, 1, TX, TY, false, K2, SHARE><<<grid, block, 0, s>>>(a);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();
 }
 
+// 2D tiles (x contiguous), one workgroup of 256 threads each; the shape is tunable.
+template <int TX, int TY, bool SHARE>
+static hipError_t launch2d(int flux, int ncomp, const StageArgs& a, hipStream_t s) {
+  return a.any_k2 ? launch2d_k<TX, TY, true, SHARE>(flux, ncomp, a, s)
+                  : launch2d_k<TX, TY, false, SHARE>(flux, ncomp, a, s);
+}
+
 hipError_t launch_stage2d_f64(int flux, int ncomp, int shape, const StageArgs& a, hipStream_t s) {
   switch (shape) {
-    case 0: return launch2d<64, 8>(flux, ncomp, a, s);
-    case 1: return launch2d<62, 8>(flux, ncomp, a, s);
-    case 2: return launch2d<126, 4>(flux, ncomp, a, s);
+    case 0: return launch2d<64, 8, true>(flux, ncomp, a, s);
+    case 1: return launch2d<62, 8, true>(flux, ncomp, a, s);
+    case 2: return launch2d<126, 4, true>(flux, ncomp, a, s);
+    case 3: return launch2d<64, 8, false>(flux, ncomp, a, s);
+    case 4: return launch2d<62, 8, false>(flux, ncomp, a, s);
+    case 5: return launch2d<126, 4, false>(flux, ncomp, a, s);
     default: return hipErrorInvalidValue;
   }
 }

@@ -27,6 +27,7 @@ using npw::Tile;
 struct npw_solver {
   int precision = NPW_FP64, flux = 0, ncomp = 1, dim = 1;
   int charw = 0;                // characteristic-wise Euler reconstruction (all instances)
+  int any_k2 = 0;               // some instance reconstructs with k = 2
   size_t esize = 8;
   int ninst = 0;
   int block = 256;              // 1D stage workgroup size (tile = block - 2 cells)
@@ -134,6 +135,7 @@ StageArgs stage_args(const npw_solver* s, int stage, int par, void* out) {
   a.out = out;
   a.stage = stage;
   a.charw = s->charw;
+  a.any_k2 = s->any_k2;
   a.spread = s->spread;
   return a;
 }
@@ -306,7 +308,7 @@ std::string tune_key(const npw_solver* s) {
   int lg = 0;
   while ((1ll << (lg + 1)) <= cells) ++lg;
   std::ostringstream k;
-  k << "v1_d" << s->dim << "_f" << s->flux << "_m" << s->ncomp << "_p" << s->precision << "_n" << lg << "_i"
+  k << "v2_d" << s->dim << "_f" << s->flux << "_m" << s->ncomp << "_p" << s->precision << "_n" << lg << "_i"
     << (s->ninst > 1 ? 1 : 0) << (s->charw ? "_c" : "");
   return k.str();
 }
@@ -567,6 +569,7 @@ static int create_common(const npw_params* p, int32_t count, const void* const* 
   s->ncomp = p[0].ncomp;
   s->dim = p[0].dim;
   s->charw = p[0].variables == NPW_CHARACTERISTIC ? 1 : 0;
+  for (int b = 0; b < count; ++b) s->any_k2 |= p[b].recon >= NPW_RBF_WENO3 ? 1 : 0;
   s->esize = p[0].precision == NPW_FP64 ? sizeof(double) : sizeof(float);
   s->ninst = count;
   s->batch = batch;
@@ -687,12 +690,14 @@ int npweno_get_stats_instance(const npw_solver* cs, int32_t index, npw_stats* st
 
 int npweno_instance_count(const npw_solver* s) { return s ? s->ninst : 0; }
 
-int npweno_launch_shape(const npw_solver* s, int32_t* block_1d, int32_t* tile_x, int32_t* tile_y) {
+int npweno_launch_shape(const npw_solver* s, int32_t* block_1d, int32_t* tile_x, int32_t* tile_y,
+                        int32_t* lds_shared) {
   if (!s) return NPW_EINVAL;
-  static const int kTx[npw::k2dShapes] = {64, 62, 126}, kTy[npw::k2dShapes] = {8, 8, 4};
+  static const int kTx[npw::k2dShapes] = {64, 62, 126, 64, 62, 126}, kTy[npw::k2dShapes] = {8, 8, 4, 8, 8, 4};
   if (block_1d) *block_1d = s->block;
   if (tile_x) *tile_x = s->dim == 2 ? kTx[s->shape2d] : 0;
   if (tile_y) *tile_y = s->dim == 2 ? kTy[s->shape2d] : 0;
+  if (lds_shared) *lds_shared = s->dim == 2 ? (s->shape2d < 3 ? 1 : 0) : 1;
   return NPW_OK;
 }
 

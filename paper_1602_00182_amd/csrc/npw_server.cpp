@@ -158,6 +158,7 @@ StageArgs pool_args(const npw_server* s, const Pool& pl, int stage, int par) {
   a.stage = stage;
   a.spread = nullptr;
   a.charw = pl.charw;
+  a.any_k2 = 1;  // requests of either order share the pool's graphs
   return a;
 }
 

@@ -107,3 +107,26 @@ def test_euler2d_other_reconstructions_fp64(recon):
         u = s.read()
     uo, _, _ = O.solve(_oracle_problem(w), w.u0, w.T, max_steps=10)
     assert np.array_equal(u, uo)
+
+
+@pytest.mark.parametrize("shape", range(6))
+@pytest.mark.parametrize("recon", [I.RBF_WENO5, I.RBF_ENO3, I.RBF_WENO3])
+def test_every_2d_launch_shape_fp64(shape, recon, monkeypatch):
+    """Each tile shape, with per-cell values shared through LDS (0-2) or recomputed per
+    interface (3-5), gives the oracle's bits on a ragged grid."""
+    _say(f"2d shape={shape} recon={recon}")
+    monkeypatch.setenv("NPW_TILE2D", str(shape))
+    w = _quadrants(131, 131).with_(recon=recon)
+    U = w.u0.reshape(4, 131, 131)[:, :37, :131].copy().reshape(-1)
+    w = w.with_(nx=131, ny=37, u0=U)
+    with B.Solver(w.u0, **B.workload_params(w)) as s:
+        ls = s.launch_shape()
+        assert (ls["tile_x"], ls["tile_y"]) == [(64, 8), (62, 8), (126, 4)][shape % 3]
+        assert ls["lds_shared"] == (1 if shape < 3 else 0)
+        L = s.rhs()
+        s.solve(w.T, max_steps=3)
+        u = s.read()
+    Lo, _ = O.rhs(_oracle_problem(w), w.u0)
+    assert np.array_equal(L, Lo)
+    uo, _, _ = O.solve(_oracle_problem(w), w.u0, w.T, max_steps=3)
+    assert np.array_equal(u, uo)
