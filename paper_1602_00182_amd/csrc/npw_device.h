@@ -57,14 +57,22 @@ __device__ __forceinline__ double div_faithful(double a, double b) {
   return fma(fma(-b, q, a), r, q);
 }
 
-// Division in the bulk precision: correctly rounded in double (the exact flavour), the plain
-// operator in float.
+// Division and square root in the bulk precision: correctly rounded in double (the exact
+// flavour); in float the hardware reciprocal and square root (about one unit in the last place
+// each), which the float bulk's tolerance absorbs.
 template <typename R>
 __device__ __forceinline__ R fdiv(R a, R b) {
   if constexpr (sizeof(R) == 8)
     return div_rn(a, b);
   else
-    return a / b;
+    return a * __builtin_amdgcn_rcpf(b);
+}
+template <typename R>
+__device__ __forceinline__ R fsqrt(R a) {
+  if constexpr (sizeof(R) == 8)
+    return sqrt(a);
+  else
+    return __builtin_amdgcn_sqrtf(a);
 }
 
 // Monotone-polynomial test of Section 4 (eqs. root_value and adaptation) on the window
@@ -419,21 +427,21 @@ __device__ __forceinline__ void char_basis(const R* UL, const R* UR, R gamma, R 
     const R vl = fdiv(UL[2], rl), vr = fdiv(UR[2], rr);
     pl = g1 * (El - R(0.5) * rl * (ul * ul + vl * vl));
     pr = g1 * (Er - R(0.5) * rr * (ur * ur + vr * vr));
-    const R sl = sqrt(rl), sr = sqrt(rr), den = sl + sr;
+    const R sl = fsqrt(rl), sr = fsqrt(rr), den = sl + sr;
     u = fdiv(sl * ul + sr * ur, den);
     v = fdiv(sl * vl + sr * vr, den);
   } else {
     pl = g1 * (El - R(0.5) * rl * ul * ul);
     pr = g1 * (Er - R(0.5) * rr * ur * ur);
-    const R sl = sqrt(rl), sr = sqrt(rr), den = sl + sr;
+    const R sl = fsqrt(rl), sr = fsqrt(rr), den = sl + sr;
     u = fdiv(sl * ul + sr * ur, den);
   }
   const R Hl = fdiv(El + pl, rl), Hr = fdiv(Er + pr, rr);
-  const R sl = sqrt(rl), sr = sqrt(rr), den = sl + sr;
+  const R sl = fsqrt(rl), sr = fsqrt(rr), den = sl + sr;
   const R H = fdiv(sl * Hl + sr * Hr, den);
   const R q2 = M == 4 ? u * u + v * v : u * u;
   const R c2 = g1 * (H - R(0.5) * q2);
-  const R c = sqrt(c2);
+  const R c = fsqrt(c2);
   const R b1 = fdiv(g1, c2), b2 = R(0.5) * b1 * q2;
   const R un = DIR == 0 ? u : v;  // normal velocity
   const R ic = fdiv(R(1.0), c);
@@ -570,7 +578,7 @@ __device__ __forceinline__ R spectral_radius(const R* U, R speed, R gamma, int& 
       bad = 2;
       return R(0);
     }
-    return fabs(u) + sqrt(fdiv(gamma * p, rho));
+    return fabs(u) + fsqrt(fdiv(gamma * p, rho));
   } else {
     R rho = U[0], u = fdiv(U[1], rho), v = fdiv(U[2], rho);
     R p = (gamma - R(1.0)) * (U[3] - R(0.5) * rho * (u * u + v * v));
@@ -578,7 +586,7 @@ __device__ __forceinline__ R spectral_radius(const R* U, R speed, R gamma, int& 
       bad = 2;
       return R(0);
     }
-    return fabs(DIR == 0 ? u : v) + sqrt(fdiv(gamma * p, rho));
+    return fabs(DIR == 0 ? u : v) + fsqrt(fdiv(gamma * p, rho));
   }
 }
 
