@@ -26,6 +26,7 @@ ADVECTION, BURGERS, EULER = 0, 1, 2
 PERIODIC, TRANSMISSIVE = 0, 1
 RBF_WENO5, WENO5_JS, RBF_ENO3, ENO3 = 0, 1, 2, 3
 RBF_WENO3, WENO3_JS, RBF_ENO2, ENO2 = 4, 5, 6, 7
+RBF_ENO2_2D = 8  # Section 6 reconstruction (2D only)
 SWITCH_MONOTONE, SWITCH_OFF = 0, 1
 OK, EINVAL, ENONFINITE, ENONPHYSICAL = 0, -1, -4, -5
 
@@ -127,6 +128,9 @@ def lib():
         L.npo_line_states.argtypes = [P, _D, ctypes.c_long, _D, _D, _D, _I]
         L.npo_char_basis.argtypes = [P, ctypes.c_int, _D, _D, _D, _D, _D]
         L.npo_char_interface.argtypes = [P, ctypes.c_int, _D, _D, _D]
+        L.npo_cross_edge.argtypes = [_D, _D, ctypes.c_int, ctypes.c_int, ctypes.c_double]
+        L.npo_cross_edge.restype = ctypes.c_double
+        L.npo_face_states.argtypes = [P, ctypes.c_int, _D, _D, _D]
         L.npo_alpha.argtypes = [P, _D, _D]
         L.npo_alpha.restype = ctypes.c_int
         L.npo_rhs.argtypes = [P, _D, _D, _D]
@@ -246,6 +250,25 @@ def char_interface(pb: Problem, direction: int, U6):
     if rc:
         raise OracleError(rc)
     return vm, vp
+
+
+def cross_edge(w3, t2, right_edge: bool, use_switch: bool = True, eps_m: float = 1e-12) -> float:
+    """Section 6 edge value of a cell from its along-sweep window w3 and transverse neighbours t2."""
+    w3, t2 = _f64(w3).copy(), _f64(t2).copy()
+    return lib().npo_cross_edge(_dp(w3), _dp(t2), int(right_edge), int(use_switch), eps_m)
+
+
+def face_states(pb: Problem, direction: int, field):
+    """Section 6 edge states (v^-, v^+) of one component field (ny x nx) along `direction`:
+    arrays of shape (lines, n + 1), interface f between cells f-1 and f."""
+    field = _f64(field).reshape(-1).copy()
+    n, lines = (pb.nx, pb.ny) if direction == 0 else (pb.ny, pb.nx)
+    vm, vp = np.zeros(lines * (n + 1)), np.zeros(lines * (n + 1))
+    p = pb.c()
+    rc = lib().npo_face_states(ctypes.byref(p), direction, _dp(field), _dp(vm), _dp(vp))
+    if rc:
+        raise OracleError(rc)
+    return vm.reshape(lines, n + 1), vp.reshape(lines, n + 1)
 
 
 def alpha(pb: Problem, u):

@@ -14,7 +14,8 @@ enum { NPO_ADVECTION = 0, NPO_BURGERS = 1, NPO_EULER = 2 };
 enum { NPO_PERIODIC = 0, NPO_TRANSMISSIVE = 1 };
 enum {
   NPO_RBF_WENO5 = 0, NPO_WENO5_JS = 1, NPO_RBF_ENO3 = 2, NPO_ENO3 = 3, /* k = 3 */
-  NPO_RBF_WENO3 = 4, NPO_WENO3_JS = 5, NPO_RBF_ENO2 = 6, NPO_ENO2 = 7  /* k = 2 */
+  NPO_RBF_WENO3 = 4, NPO_WENO3_JS = 5, NPO_RBF_ENO2 = 6, NPO_ENO2 = 7, /* k = 2 */
+  NPO_RBF_ENO2_2D = 8 /* k = 2, Section 6: shape parameter from the five-cell cross (2D only) */
 };
 enum { NPO_SWITCH_MONOTONE = 0, NPO_SWITCH_OFF = 1 };
 
@@ -56,6 +57,8 @@ void npo_line_states(const npo_problem* pb, const double* line, long n, double* 
 int npo_char_basis(const npo_problem* pb, int dir, const double* UL, const double* UR, double* Lm, double* Rm,
                    double* lam);
 int npo_char_interface(const npo_problem* pb, int dir, const double* U6, double* vm, double* vp);
+double npo_cross_edge(const double w3[3], const double t2[2], int right_edge, int use_switch, double eps_m);
+int npo_face_states(const npo_problem* pb, int dir, const double* field, double* vm, double* vp);
 int npo_alpha(const npo_problem* pb, const double* u, double alpha[2]);
 int npo_rhs(const npo_problem* pb, const double* u, double* L, double alpha_out[2]);
 int npo_step(const npo_problem* pb, double* u, double T, double* t, double* dt_out);
