@@ -60,10 +60,13 @@ enum { NPW_FP64 = 0, NPW_FP32 = 1 };  /* bulk precision; eta, the switch test, d
  * RBF-ENO3 (one stencil chosen by Newton divided differences, Section 2, perturbed with the same
  * eta and switch) and ENO3 (its eta = 0 limit).  k = 2 (Table 2, shape parameter of Section 3.2
  * per cell and edge): RBF-WENO3, WENO3-JS, RBF-ENO2 and ENO2; their Section 4 switch zeroes both
- * edge parameters of a cell whose three-cell window is not monotone. */
+ * edge parameters of a cell whose three-cell window is not monotone.  NPW_RBF_ENO2_2D (2D only,
+ * Section 6): the ENO2 edge value perturbed with a shape parameter from the five-cell cross of the
+ * cell (second differences along and across the sweep over the printed edge estimate). */
 enum {
   NPW_RBF_WENO5 = 0, NPW_WENO5_JS = 1, NPW_RBF_ENO3 = 2, NPW_ENO3 = 3,
-  NPW_RBF_WENO3 = 4, NPW_WENO3_JS = 5, NPW_RBF_ENO2 = 6, NPW_ENO2 = 7
+  NPW_RBF_WENO3 = 4, NPW_WENO3_JS = 5, NPW_RBF_ENO2 = 6, NPW_ENO2 = 7,
+  NPW_RBF_ENO2_2D = 8
 };
 enum { NPW_SWITCH_MONOTONE = 0, NPW_SWITCH_OFF = 1 };        /* Section 4 switch on / off */
 /* Variables the Euler equations are reconstructed in.  Component-wise is the scheme as the paper
@@ -80,7 +83,7 @@ typedef struct {
   int32_t ncomp;       /* 1 for scalar fluxes, 3 for 1D Euler, 4 for 2D Euler */
   int32_t bc;          /* NPW_PERIODIC or NPW_TRANSMISSIVE (copy of the edge cell) */
   int32_t precision;   /* NPW_FP64 or NPW_FP32 */
-  int32_t recon;       /* NPW_RBF_WENO5 .. NPW_ENO2 (k = 3 or k = 2, see above) */
+  int32_t recon;       /* NPW_RBF_WENO5 .. NPW_RBF_ENO2_2D (k = 3 or k = 2, see above) */
   int32_t switch_mode; /* NPW_SWITCH_MONOTONE or NPW_SWITCH_OFF */
   int64_t nx, ny;      /* cells per direction; ny is ignored (treated as 1) in 1D */
   double x0, x1, y0, y1;   /* domain; y0, y1 ignored in 1D */

@@ -274,6 +274,7 @@ struct ReconMode {
   bool eno;         // one stencil per cell (ENO) instead of the weighted combination
   bool use_eta;     // the multiquadric perturbation is on
   bool use_switch;  // the Section 4 switch zeroes it near non-monotone windows
+  bool cross;       // Section 6: k = 2 with the shape parameter from the five-cell cross (2D)
 };
 __device__ __forceinline__ ReconMode recon_mode(int recon, int sw) {
   ReconMode m;
@@ -281,6 +282,8 @@ __device__ __forceinline__ ReconMode recon_mode(int recon, int sw) {
   m.eno = recon == NPW_RBF_ENO3 || recon == NPW_ENO3 || recon == NPW_RBF_ENO2 || recon == NPW_ENO2;
   m.use_eta = recon == NPW_RBF_WENO5 || recon == NPW_RBF_ENO3 || recon == NPW_RBF_WENO3 || recon == NPW_RBF_ENO2;
   m.use_switch = m.use_eta && sw == NPW_SWITCH_MONOTONE;
+  m.cross = recon == NPW_RBF_ENO2_2D;
+  if (m.cross) m.use_eta = false, m.use_switch = sw == NPW_SWITCH_MONOTONE;
   return m;
 }
 
@@ -362,6 +365,42 @@ template <typename R, bool PLUS>
 __device__ __forceinline__ R eno2(int r, R a, R b, R c, R eta) {
   if (r == 0) return PLUS ? table2_row<R, -1>(b, c, eta) : table2_row<R, 0>(b, c, eta);
   return PLUS ? table2_row<R, 0>(a, b, eta) : table2_row<R, 1>(a, b, eta);
+}
+
+// Section 6 edge value of a cell from its three cells along the sweep (a, b, c) and its two
+// transverse neighbours (ts, tn): the ENO2 polynomial value P of the pair chosen by divided
+// differences (the transverse cell of the 2D stencil weighs 0 at the edge midpoint), perturbed to
+// P + eta P with eta = (K dxx + dyy) / (4 D +- eps_M): dxx, dyy the second differences along and
+// across the sweep, K = 4 for the centred pair and -8 for the extrapolating one (each cancels its
+// pair's Taylor error), D the printed edge estimate (-2, 1, -5), mirrored for the left edge.  The
+// switch keeps P when either three-cell window of the cell is not monotone.  RIGHT: the edge at
+// the cell's + side (v^-), else its - side (v^+).  eta is double; the double flavour evaluates
+// every operation in this order, uncontracted, with correctly rounded division.
+template <typename R, bool RIGHT>
+__device__ __forceinline__ R cross_edge(R a, R b, R c, R ts, R tn, bool use_switch, double eps_m) {
+#pragma clang fp contract(off)
+  constexpr bool kCR = sizeof(R) == 8;
+  const double da = double(a), db = double(b), dc = double(c);
+  const int r = eno2_stencil(da, db, dc);  // 1: {k-1, k}, 0: {k, k+1}
+  R P;
+  if (RIGHT)
+    P = r == 0 ? table2_row<R, 0>(b, c, R(0)) : table2_row<R, 1>(a, b, R(0));
+  else
+    P = r == 0 ? table2_row<R, -1>(b, c, R(0)) : table2_row<R, 0>(a, b, R(0));
+  if (use_switch && (monotone_flag<kCR>(da, db, dc) | monotone_flag<kCR>(double(ts), db, double(tn)))) return P;
+  const double dxx = da - 2.0 * db + dc;
+  const double dyy = double(ts) - 2.0 * db + double(tn);
+  const double D = RIGHT ? -2.0 * da + db - 5.0 * dc : -2.0 * dc + db - 5.0 * da;
+  const bool centred = RIGHT ? r == 0 : r == 1;
+  const double K = centred ? 4.0 : -8.0;
+  const double num = K * dxx + dyy;
+  double den = 4.0 * D;
+  if (den >= 0.0)
+    den = den + eps_m;
+  else
+    den = den - eps_m;
+  const double eta = kCR ? div_rn(num, den) : div_faithful(num, den);
+  return P + R(eta) * P;
 }
 
 // States at one interface x_{i+1/2} of one scalar field from its six-cell window

@@ -145,7 +145,7 @@ __global__ __launch_bounds__(256) void stage2d_kernel(StageArgs a) {
   const R rdt = R(dt);
   ReconMode rm = recon_mode(I->recon, I->sw);
   if (!K2) rm.k2 = false;  // launched for a k = 3 instance
-  const bool k2 = rm.k2, eno = rm.eno, use_eta = rm.use_eta, use_switch = rm.use_switch;
+  const bool k2 = rm.k2, eno = rm.eno, use_eta = rm.use_eta, use_switch = rm.use_switch, cross = rm.cross;
   const double eps_m = I->eps_m;
   const R eps = R(I->eps_weno);
   const R speed_x = R(I->speed_x), speed_y = R(I->speed_y), gamma = R(I->gamma);
@@ -175,7 +175,7 @@ __global__ __launch_bounds__(256) void stage2d_kernel(StageArgs a) {
     auto cid = [&](int line, int pos) -> int { return DIR == 0 ? line * NPOS + pos + 1 : (pos + 1) * LINES + line; };
     // cell phase: flag and weight denominators of cells -1..LEN of every line (none in the
     // characteristic mode: its fields belong to an interface)
-    for (int w = tid; w < (CHAR ? 0 : NPOS * LINES); w += BS) {
+    for (int w = tid; w < (CHAR || cross ? 0 : NPOS * LINES); w += BS) {
       const int line = DIR == 0 ? w / NPOS : w % LINES;
       const int pos = DIR == 0 ? w % NPOS - 1 : w / LINES - 1;
       const int q = pos + 3;
@@ -230,6 +230,13 @@ __global__ __launch_bounds__(256) void stage2d_kernel(StageArgs a) {
       }
 #pragma unroll
       for (int c = 0; c < (CHAR ? 0 : M); ++c) {
+        if (k2 && cross) {  // Section 6: transverse neighbours are the adjacent lines
+          A[c] = cross_edge<R, true>(U(c, line, q - 1), U(c, line, q), U(c, line, q + 1), U(c, line - 1, q),
+                                     U(c, line + 1, q), use_switch, eps_m);
+          B[c] = cross_edge<R, false>(U(c, line, q), U(c, line, q + 1), U(c, line, q + 2), U(c, line - 1, q + 1),
+                                      U(c, line + 1, q + 1), use_switch, eps_m);
+          continue;
+        }
         if (k2) {
           R el, er;
           if constexpr (SHARE) {

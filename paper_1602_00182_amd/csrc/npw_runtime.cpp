@@ -84,7 +84,8 @@ int validate(const npw_params* p) {
   }
   if (p->bc != NPW_PERIODIC && p->bc != NPW_TRANSMISSIVE) return NPW_EINVAL;
   if (p->precision != NPW_FP64 && p->precision != NPW_FP32) return NPW_EINVAL;
-  if (p->recon < NPW_RBF_WENO5 || p->recon > NPW_ENO2) return NPW_EINVAL;
+  if (p->recon < NPW_RBF_WENO5 || p->recon > NPW_RBF_ENO2_2D) return NPW_EINVAL;
+  if (p->recon == NPW_RBF_ENO2_2D && (p->dim != 2 || p->variables != NPW_COMPONENTWISE)) return NPW_EINVAL;
   if (p->switch_mode != NPW_SWITCH_MONOTONE && p->switch_mode != NPW_SWITCH_OFF) return NPW_EINVAL;
   if (!(std::isfinite(p->x0) && std::isfinite(p->x1) && p->x1 > p->x0)) return NPW_EINVAL;
   if (p->dim == 2 && !(std::isfinite(p->y0) && std::isfinite(p->y1) && p->y1 > p->y0)) return NPW_EINVAL;

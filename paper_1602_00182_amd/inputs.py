@@ -28,6 +28,7 @@ ADVECTION, BURGERS, EULER = 0, 1, 2
 PERIODIC, TRANSMISSIVE = 0, 1
 RBF_WENO5, WENO5_JS, RBF_ENO3, ENO3 = 0, 1, 2, 3  # k = 3 (Table 3)
 RBF_WENO3, WENO3_JS, RBF_ENO2, ENO2 = 4, 5, 6, 7  # k = 2 (Table 2)
+RBF_ENO2_2D = 8  # k = 2, Section 6 (2D only)
 SWITCH_MONOTONE, SWITCH_OFF = 0, 1
 COMPONENTWISE, CHARACTERISTIC = 0, 1
 

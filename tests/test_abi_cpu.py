@@ -55,7 +55,7 @@ def test_params_struct_matches_header_defaults(L):
 @pytest.mark.parametrize("bad", [
     {"nx": 0}, {"flux": 7}, {"flux": 2, "ncomp": 1}, {"ncomp": 3}, {"bc": 5}, {"precision": 3},
     {"cfl": 0.0}, {"cfl": float("nan")}, {"eps_weno": -1.0}, {"eps_m": 0.0}, {"x1": -2.0},
-    {"abi_version": 99}, {"recon": 8}, {"switch_mode": 9}, {"dt_fixed": -1.0},
+    {"abi_version": 99}, {"recon": 8}, {"recon": 9}, {"switch_mode": 9}, {"dt_fixed": -1.0},
     {"flux": 2, "ncomp": 3, "gamma": 1.0}, {"variables": 1}, {"flux": 2, "ncomp": 3, "variables": 2},
     {"reserved": 1},
 ])

@@ -97,3 +97,27 @@ def test_batch_second_solve_continues():
             uo, t1, _ = O.solve(_oracle_problem(w), w.u0, 0.05 * (b + 1))
             uo, _, _ = O.solve(_oracle_problem(w), uo, 0.3, t=t1)
             assert np.array_equal(bt.read(b), uo), b
+
+
+def test_full_size_riemann_batch_sampled_fp32():
+    """The 4096-instance Riemann batch in the benchmark's form (float bulk, one launch per stage,
+    autotuned block), 25 steps: sampled instances agree with the FP64 oracle on their float
+    inputs and with their own solo solves bit for bit."""
+    _say("full-size riemann batch fp32 (4096 instances)")
+    ws = I.euler_riemann_batch(count=4096, seed=3)
+    states = _states(ws, B.FP32)
+    T = [w.T for w in ws]
+    with B.Batch(states, [B.workload_params(w, B.FP32) for w in ws]) as bt:
+        stats, rc = bt.solve(T, 25)
+        assert rc == B.OK
+        picks = [0, 1, 777, 2048, 3001, 4095]
+        got = {b: bt.read(b) for b in picks}
+    for b in picks:
+        w = ws[b]
+        assert stats[b]["nsteps"] == 25
+        uo, _, _ = O.solve(_oracle_problem(w), states[b].astype(np.float64), w.T, max_steps=25)
+        # Riemann data: the jump makes a few cells sensitive to rounding (L1 bound, as for Sod)
+        assert np.mean(np.abs(got[b] - uo)) <= 1e-4, b
+        with B.Solver(states[b], **B.workload_params(w, B.FP32)) as s:
+            s.solve(w.T, 25)
+            assert np.array_equal(s.read(), got[b]), b
