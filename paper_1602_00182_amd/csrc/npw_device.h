@@ -85,15 +85,20 @@ __device__ __forceinline__ R fsqrt(R a) {
 // same decision without the quotient: 0 < num/den < 3 holds exactly when num and den are non-zero
 // with one sign and num lies on the near side of 3 den.  A quotient of such operands cannot lie
 // within rounding distance of 0 or 3 without equalling it, so both forms decide alike.
+// In the float bulk the window's doubles are float values, so the differences p = u0 - um1 and
+// q = up1 - u0 and every small-integer combination of them below are exact; num = 2p - q and
+// den = p - q are then the same numbers as the forms written above, in fewer operations.
 template <bool CR = true>
 __device__ __forceinline__ int monotone_flag(double um1, double u0, double up1) {
 #pragma clang fp contract(off)
-  double num = -2.0 * um1 + 3.0 * u0 - up1;
-  double den = -um1 + 2.0 * u0 - up1;
   if constexpr (CR) {
+    double num = -2.0 * um1 + 3.0 * u0 - up1;
+    double den = -um1 + 2.0 * u0 - up1;
     double xp = div_rn(num, den);
     return (xp > 0.0 && xp < 3.0) ? 1 : 0;
   } else {
+    const double p = u0 - um1, q = up1 - u0;
+    const double num = fma(2.0, p, -q), den = p - q;
     if (num == 0.0 || den == 0.0 || (num > 0.0) != (den > 0.0)) return 0;
     return (den > 0.0 ? num < 3.0 * den : num > 3.0 * den) ? 1 : 0;
   }
@@ -102,11 +107,19 @@ __device__ __forceinline__ int monotone_flag(double um1, double u0, double up1) 
 // Shape parameter eta = eps^2 dx^2 at x_{i+1/2} (Table 3 caption) from u_{i-1}..u_{i+2}:
 // third over (weighted) first undivided difference; eps_M is added with the sign of the
 // denominator so that it never crosses zero.  Double precision, uncontracted.
+// (Float bulk: with s = um1 - up2 and d = up1 - u0, both exact, num = s + 3d and den = s + 15d.)
 template <bool CR = true>
 __device__ __forceinline__ double eta_ratio(double um1, double u0, double up1, double up2, double eps_m) {
 #pragma clang fp contract(off)
-  double num = um1 - 3.0 * u0 + 3.0 * up1 - up2;
-  double den = um1 - 15.0 * u0 + 15.0 * up1 - up2;
+  double num, den;
+  if constexpr (CR) {
+    num = um1 - 3.0 * u0 + 3.0 * up1 - up2;
+    den = um1 - 15.0 * u0 + 15.0 * up1 - up2;
+  } else {
+    const double sd = um1 - up2, d = up1 - u0;
+    num = fma(3.0, d, sd);
+    den = fma(15.0, d, sd);
+  }
   if (den >= 0.0)
     den = den + eps_m;
   else
@@ -308,7 +321,7 @@ __device__ __forceinline__ R table2_row(R w0, R w1, R eta) {
 template <bool CR = true>
 __device__ __forceinline__ double eta2_ratio(double ufar, double u0, double unear, double eps_m) {
 #pragma clang fp contract(off)
-  double num = 2.0 * (-ufar + 2.0 * u0 - unear);
+  double num = CR ? 2.0 * (-ufar + 2.0 * u0 - unear) : 2.0 * ((u0 - ufar) - (unear - u0));
   double den = -ufar + 5.0 * u0 + 2.0 * unear;
   if (den >= 0.0)
     den = den + eps_m;

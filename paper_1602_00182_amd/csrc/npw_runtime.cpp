@@ -694,7 +694,8 @@ int npweno_instance_count(const npw_solver* s) { return s ? s->ninst : 0; }
 int npweno_launch_shape(const npw_solver* s, int32_t* block_1d, int32_t* tile_x, int32_t* tile_y,
                         int32_t* lds_shared) {
   if (!s) return NPW_EINVAL;
-  static const int kTx[npw::k2dShapes] = {64, 62, 126, 64, 62, 126}, kTy[npw::k2dShapes] = {8, 8, 4, 8, 8, 4};
+  static const int kTx[npw::k2dShapes] = {64, 62, 126, 64, 62, 126};
+  static const int kTy[npw::k2dShapes] = {8, 8, 4, 8, 8, 4};
   if (block_1d) *block_1d = s->block;
   if (tile_x) *tile_x = s->dim == 2 ? kTx[s->shape2d] : 0;
   if (tile_y) *tile_y = s->dim == 2 ? kTy[s->shape2d] : 0;
