@@ -699,11 +699,27 @@ __device__ __forceinline__ R wave_max_nonneg(R v) {
   }
 }
 
-// alpha of (slot, dir) for every lane: the max of the kSpread entries (one per lane, then DPP).
-__device__ __forceinline__ unsigned long long spread_read(const unsigned long long* spread, int slot, int dir) {
-  const int lane = threadIdx.x & 63;
-  const unsigned long long v = spread[((slot * 2 + dir) * kSpread + lane) * kSpreadStride];
-  return double_to_bits(wave_max_nonneg(bits_to_double(v)));
+// Float-bulk single grids tag every spread alpha entry with the stage that wrote it:
+// entry = (stage sequence << 32) | float bits of alpha, the sequence of RK stage k of step n being
+// 3n + k and that of the state check of u^n being 3n.  Newer tags win the atomicMax, and a reader
+// keeps only the entries carrying the sequence it expects, so no kernel has to clear a slot (the
+// state check clears all of them whenever the state is replaced).
+__device__ __forceinline__ unsigned long long spread_tag(long long seq, float a) {
+  return ((unsigned long long)(unsigned)seq << 32) | (unsigned long long)__float_as_uint(a);
 }
+// max over the wave's entries that carry the expected sequence (one entry per lane), as double bits
+__device__ __forceinline__ unsigned long long spread_reduce_tagged(unsigned long long entry, long long expect) {
+  const float v = (unsigned)(entry >> 32) == (unsigned)expect ? __uint_as_float((unsigned)entry) : 0.0f;
+  return double_to_bits(double(wave_max_nonneg<float>(v)));
+}
+// max over the wave's untagged entries (double bulk), as double bits
+__device__ __forceinline__ unsigned long long spread_reduce(unsigned long long entry) {
+  return double_to_bits(wave_max_nonneg(bits_to_double(entry)));
+}
+// This lane's entry of (slot, dir).
+__device__ __forceinline__ unsigned long long spread_entry(const unsigned long long* spread, int slot, int dir) {
+  return spread[((slot * 2 + dir) * kSpread + (threadIdx.x & 63)) * kSpreadStride];
+}
+
 
 }  // namespace npw

@@ -69,16 +69,29 @@ __device__ __forceinline__ void stage1d_tile(const StageArgs& a, const Tile tile
   unsigned long long* sp = a.spread;
   const bool lead = (start == 0 && tid == 0);
   const bool lead_wave = (start == 0 && tid < 64);
+  // float bulk: spread entries carry the stage sequence that wrote them (spread_tag)
+  constexpr bool kTag = !kExact;
+  const int slot_in = stage == 0 ? 0 : stage - 1;
+  const unsigned long long sp_e = sp ? spread_entry(sp, slot_in, 0) : 0ull;
   const int err = I->err;
   const Ctl c0 = I->ctl[0], c1 = I->ctl[1], c2 = I->ctl[2];
-  const int slot_in = stage == 0 ? 0 : stage - 1;
-  const unsigned long long alpha_bits = sp ? spread_read(sp, slot_in, 0) : I->alpha[slot_in][0];
+  unsigned long long alpha_bits;
+  if (sp) {
+    if constexpr (kTag) {
+      const long long n_in = stage <= 1 ? c0.n : (stage == 2 ? c1.n : c2.n);
+      alpha_bits = spread_reduce_tagged(sp_e, 3 * n_in + slot_in);
+    } else {
+      alpha_bits = spread_reduce(sp_e);
+    }
+  } else {
+    alpha_bits = I->alpha[slot_in][0];
+  }
   const double T = I->T, tol = I->tol;
   const double dt_fixed = I->dt_fixed, cfl = I->cfl, dxd = I->dx;
-  // zero an alpha slot before the kernel that accumulates into it runs
+  // zero an alpha slot before the kernel that accumulates into it runs (tagged slots need not be)
   auto zero_slot = [&](int slot) {
     if (sp) {
-      if (lead_wave) {
+      if (!kTag && lead_wave) {
         sp[((slot * 2 + 0) * kSpread + tid) * kSpreadStride] = 0ull;
         sp[((slot * 2 + 1) * kSpread + tid) * kSpreadStride] = 0ull;
       }
@@ -297,7 +310,11 @@ __device__ __forceinline__ void stage1d_tile(const StageArgs& a, const Tile tile
         I->err_home = par;
       }
     } else {
-      atomicMax(sp ? &sp[((slot * 2 + 0) * kSpread + blockIdx.x % kSpread) * kSpreadStride] : &I->alpha[slot][0], m);
+      if (sp && kTag)
+        atomicMax(&sp[((slot * 2 + 0) * kSpread + blockIdx.x % kSpread) * kSpreadStride],
+                  spread_tag(3 * n + stage, float(bits_to_double(m))));
+      else
+        atomicMax(sp ? &sp[((slot * 2 + 0) * kSpread + blockIdx.x % kSpread) * kSpreadStride] : &I->alpha[slot][0], m);
     }
   }
 }
@@ -398,7 +415,7 @@ __global__ __launch_bounds__(256) void check_partial_kernel(InstDev* inst, void*
 }
 
 static __global__ __launch_bounds__(64) void check_final_kernel(InstDev* inst, int ninst, const CheckPartial* part, int G,
-                                                         int ncomp, unsigned long long* spread) {
+                                                                int ncomp, unsigned long long* spread, int tagged) {
   const int b = blockIdx.x * 64 + threadIdx.x;
   if (spread && blockIdx.x == 0) {  // single grid: entry 0 of slot 0 holds alpha, every other entry starts at 0
     for (int k = threadIdx.x; k < 3 * 2 * kSpread; k += 64) spread[k * kSpreadStride] = 0ull;
@@ -420,9 +437,10 @@ static __global__ __launch_bounds__(64) void check_final_kernel(InstDev* inst, i
   for (int c = 0; c < 4; ++c) I->mass[c] = c < ncomp ? tot[c] * area : 0.0;
   I->alpha[0][0] = mx;
   I->alpha[0][1] = my;
-  if (spread) {
-    spread[(0 * kSpread + 0) * kSpreadStride] = mx;
-    spread[(1 * kSpread + 0) * kSpreadStride] = my;
+  if (spread) {  // the state of step n opens sequence 3n (see spread_tag)
+    const long long seq = 3 * I->ctl[0].n;
+    spread[(0 * kSpread + 0) * kSpreadStride] = tagged ? spread_tag(seq, float(bits_to_double(mx))) : mx;
+    spread[(1 * kSpread + 0) * kSpreadStride] = tagged ? spread_tag(seq, float(bits_to_double(my))) : my;
   }
   if (w) {
     I->err = w == 2 ? NPW_ENONPHYSICAL : NPW_ENONFINITE;

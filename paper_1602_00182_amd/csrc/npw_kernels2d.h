@@ -78,16 +78,31 @@ __global__ __launch_bounds__(256) void stage2d_kernel(StageArgs a) {
   unsigned long long* sp = a.spread;
   const bool first_block = (blockIdx.x == 0 && blockIdx.y == 0);
   const bool lead = first_block && tid == 0;
+  constexpr bool kTag = !kExact;  // float bulk: spread entries carry their stage sequence
+  const int slot_in = stage == 0 ? 0 : stage - 1;
+  const unsigned long long spx = sp ? spread_entry(sp, slot_in, 0) : 0ull;
+  const unsigned long long spy = sp ? spread_entry(sp, slot_in, 1) : 0ull;
   const int err = I->err;
   const Ctl c0 = I->ctl[0], c1 = I->ctl[1], c2 = I->ctl[2];
-  const int slot_in = stage == 0 ? 0 : stage - 1;
-  const unsigned long long ax_bits = sp ? spread_read(sp, slot_in, 0) : I->alpha[slot_in][0];
-  const unsigned long long ay_bits = sp ? spread_read(sp, slot_in, 1) : I->alpha[slot_in][1];
+  unsigned long long ax_bits, ay_bits;
+  if (sp) {
+    if constexpr (kTag) {
+      const long long n_in = stage <= 1 ? c0.n : (stage == 2 ? c1.n : c2.n);
+      ax_bits = spread_reduce_tagged(spx, 3 * n_in + slot_in);
+      ay_bits = spread_reduce_tagged(spy, 3 * n_in + slot_in);
+    } else {
+      ax_bits = spread_reduce(spx);
+      ay_bits = spread_reduce(spy);
+    }
+  } else {
+    ax_bits = I->alpha[slot_in][0];
+    ay_bits = I->alpha[slot_in][1];
+  }
   const double T = I->T, tol = I->tol;
   const double dt_fixed = I->dt_fixed, cfl = I->cfl, dxd = I->dx, dyd = I->dy;
   auto zero_slot = [&](int slot) {
     if (sp) {
-      if (first_block && tid < 64) {
+      if (!kTag && first_block && tid < 64) {
         sp[((slot * 2 + 0) * kSpread + tid) * kSpreadStride] = 0ull;
         sp[((slot * 2 + 1) * kSpread + tid) * kSpreadStride] = 0ull;
       }
@@ -387,8 +402,13 @@ __global__ __launch_bounds__(256) void stage2d_kernel(StageArgs a) {
       }
     } else {
       const int k = (blockIdx.y * gridDim.x + blockIdx.x) % kSpread;
-      atomicMax(sp ? &sp[((slot * 2 + 0) * kSpread + k) * kSpreadStride] : &I->alpha[slot][0], mx);
-      atomicMax(sp ? &sp[((slot * 2 + 1) * kSpread + k) * kSpreadStride] : &I->alpha[slot][1], my);
+      if (sp && kTag) {
+        atomicMax(&sp[((slot * 2 + 0) * kSpread + k) * kSpreadStride], spread_tag(3 * n + stage, float(bits_to_double(mx))));
+        atomicMax(&sp[((slot * 2 + 1) * kSpread + k) * kSpreadStride], spread_tag(3 * n + stage, float(bits_to_double(my))));
+      } else {
+        atomicMax(sp ? &sp[((slot * 2 + 0) * kSpread + k) * kSpreadStride] : &I->alpha[slot][0], mx);
+        atomicMax(sp ? &sp[((slot * 2 + 1) * kSpread + k) * kSpreadStride] : &I->alpha[slot][1], my);
+      }
     }
   }
 }

@@ -88,7 +88,7 @@ hipError_t launch_init_f64(int flux, int ncomp, InstDev* inst, int ninst, void* 
     return hipErrorInvalidValue;
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  check_final_kernel<<<(ninst + 63) / 64, 64, 0, s>>>(inst, ninst, part, G, ncomp, spread);
+  check_final_kernel<<<(ninst + 63) / 64, 64, 0, s>>>(inst, ninst, part, G, ncomp, spread, 0);
   return hipGetLastError();
 }
 
