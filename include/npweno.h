@@ -1,5 +1,5 @@
 /*
- * npweno.h -- C ABI of the MI355X (gfx950) non-polynomial WENO5 finite-volume library.
+ * npweno.h -- C ABI of the MI355X (gfx950) non-polynomial ENO/WENO finite-volume library.
  *
  * The library solves the hyperbolic conservation law u_t + div F(u) = 0 (Section 1 of Guo &
  * Jung, "Non-polynomial ENO and WENO finite volume methods for hyperbolic conservation laws",
@@ -15,6 +15,9 @@
  *     method (Section 5.1),
  *   - in 2D, the dimension-by-dimension finite-volume form of Section 7 (eq. 2DIntegral) with
  *     one midpoint quadrature point per face.
+ * The same kernels also run the ENO selection of Section 2, the k = 2 reconstructions of Table 2,
+ * the two-dimensional k = 2 reconstruction of Section 6, and (an extension) characteristic-wise
+ * reconstruction of the Euler equations.
  * All compute runs in HIP kernels on the device; nothing falls back to the CPU.
  *
  * Conventions for every entry point:

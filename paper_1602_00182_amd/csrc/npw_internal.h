@@ -82,7 +82,6 @@ constexpr int kSpreadWords = 3 * 2 * kSpread * kSpreadStride;
 // Launchers implemented in the kernel translation units (one per bulk precision).
 hipError_t launch_stage_f64(int flux, int ncomp, int block, const StageArgs& a, hipStream_t s);
 hipError_t launch_stage_f32(int flux, int ncomp, int block, const StageArgs& a, hipStream_t s);
-// Recompute alpha slot 0, finiteness/physicality checks and the per-component sums of u^n.
 // 2D launch shapes: tiles 0 = 64 x 8, 1 = 62 x 8, 2 = 126 x 4 cells with per-cell values shared
 // through LDS; 3, 4, 5 = the same tiles with those values recomputed per interface.  (Taller
 // recomputed tiles, 64 x 12 and 64 x 16, do less halo work along y but hold more LDS; measured
@@ -90,7 +89,9 @@ hipError_t launch_stage_f32(int flux, int ncomp, int block, const StageArgs& a, 
 constexpr int k2dShapes = 6;
 hipError_t launch_stage2d_f64(int flux, int ncomp, int shape, const StageArgs& a, hipStream_t s);
 hipError_t launch_stage2d_f32(int flux, int ncomp, int shape, const StageArgs& a, hipStream_t s);
-// scratch holds G * ninst partial records (kCheckPartialBytes each); G workgroups per instance.
+// State check of u^n for ninst instances: alpha slot 0 (and the spread entries of a single grid),
+// finiteness/physicality and the per-component FP64 sums.  scratch holds G * ninst partial
+// records (kCheckPartialBytes each); G workgroups per instance.
 constexpr int kCheckPartialBytes = 56;
 hipError_t launch_init_f64(int flux, int ncomp, InstDev* inst, int ninst, void* P0, void* P1,
                            unsigned long long* spread, void* scratch, int G, hipStream_t s);

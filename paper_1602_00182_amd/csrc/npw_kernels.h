@@ -349,6 +349,7 @@ struct CheckPartial {
   unsigned long long ax, ay;
   int bad, pad;
 };
+static_assert(sizeof(CheckPartial) == kCheckPartialBytes, "scratch is sized with kCheckPartialBytes");
 
 template <typename R, int FLUX, int M>
 __global__ __launch_bounds__(256) void check_partial_kernel(InstDev* inst, void* P0, void* P1, CheckPartial* part,
