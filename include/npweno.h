@@ -88,7 +88,8 @@ typedef struct {
   int32_t precision;   /* NPW_FP64 or NPW_FP32 */
   int32_t recon;       /* NPW_RBF_WENO5 .. NPW_RBF_ENO2_2D (k = 3 or k = 2, see above) */
   int32_t switch_mode; /* NPW_SWITCH_MONOTONE or NPW_SWITCH_OFF */
-  int64_t nx, ny;      /* cells per direction; ny is ignored (treated as 1) in 1D */
+  int64_t nx, ny;      /* cells per direction; ny is ignored (treated as 1) in 1D.  Limits:
+                        * 1D ncomp * nx <= 2^31 - 2^16; 2D nx <= 2^30, ny <= 262140 */
   double x0, x1, y0, y1;   /* domain; y0, y1 ignored in 1D */
   double speed_x, speed_y; /* advection velocity (NPW_ADVECTION) */
   double gamma;            /* ratio of specific heats (NPW_EULER), > 1 */

@@ -56,6 +56,9 @@ struct npw_solver {
   std::vector<char> settled;       // per instance: error already handled
 };
 
+constexpr long long kMaxNy2D = 4LL * 65535;  // tallest 2D grid (126 x 4 tiles, 65535 rows of them)
+constexpr long long kMaxElems1D = (1LL << 31) - (1LL << 16);  // largest 1D instance, ncomp * nx
+
 namespace {
 
 constexpr int kMaxGraphSteps = 256;  // steps per captured graph (3 stage kernels each)
@@ -73,7 +76,11 @@ int validate(const npw_params* p) {
   if (p->abi_version != NPW_ABI_VERSION) return NPW_EINVAL;
   if (p->dim != 1 && p->dim != 2) return NPW_EINVAL;
   if (p->nx < 1 || (p->dim == 2 && p->ny < 1)) return NPW_EINVAL;
-  if (p->nx > (1 << 30) || (p->dim == 2 && p->ny > (1 << 30))) return NPW_EINVAL;
+  // 1D kernels index an instance's state with 32-bit integers, including the ghost and halo cells
+  // of its last tile (up to BS + 3 past nx), so ncomp * nx keeps a 2^16 margin below 2^31; the 2D
+  // grid spans ceil(ny / 4) workgroups along y, at most 65535.
+  if (p->dim == 1 && (long long)(p->ncomp > 0 ? p->ncomp : 1) * p->nx > kMaxElems1D) return NPW_EINVAL;
+  if (p->dim == 2 && (p->nx > (1 << 30) || p->ny > kMaxNy2D)) return NPW_EINVAL;
   if (p->flux == NPW_ADVECTION || p->flux == NPW_BURGERS) {
     if (p->ncomp != 1) return NPW_EINVAL;
   } else if (p->flux == NPW_EULER) {
@@ -222,6 +229,7 @@ void clear_graphs(npw_solver* s) {
 // or when at most 3/4 of its tiles still belong to running instances.  Graphs hold the tile
 // count, so they are re-captured when it changes.
 int set_tiles(npw_solver* s, const std::vector<char>& want, bool force) {
+  if (!s->batch) return NPW_OK;  // a single grid derives its tiles from the block index
   std::vector<Tile> t;
   t.reserve(s->tiles_all.size());
   for (const Tile& x : s->tiles_all)
@@ -263,6 +271,7 @@ int reset_instances(npw_solver* s, double t);
 constexpr int kBlocks[3] = {128, 256, 512};
 
 size_t max_tiles(const npw_solver* s) {
+  if (!s->batch) return 1;  // no table: tiles follow from the block index
   size_t n = 0;
   for (const InstDev& h : s->h_inst) n += (size_t)((h.nx + kBlocks[0] - 3) / (kBlocks[0] - 2));
   return std::max<size_t>(n, 1);
@@ -272,6 +281,18 @@ size_t max_tiles(const npw_solver* s) {
 void build_tiles(npw_solver* s) {
   const int tile = s->block - 2;
   s->tiles_all.clear();
+  if (!s->batch) {  // one placeholder entry; the grid covers ceil(nx / tile) tiles
+    const InstDev& h = s->h_inst[0];
+    Tile t;
+    t.inst = 0;
+    t.bc = h.bc;
+    t.start = 0;
+    t.nx = h.nx;
+    t.off = 0;
+    s->tiles_all.push_back(t);
+    s->ntiles = (int)((h.nx + tile - 1) / tile);
+    return;
+  }
   for (int b = 0; b < s->ninst; ++b) {
     const InstDev& h = s->h_inst[b];
     for (long long st = 0; st < h.nx; st += tile) {
@@ -581,9 +602,8 @@ static int create_common(const npw_params* p, int32_t count, const void* const* 
     s->h_inst.push_back(make_inst(&p[b], off));
     off += (long long)p[b].ncomp * p[b].nx * (p[b].dim == 2 ? p[b].ny : 1);
   }
-  build_tiles(s);
+  build_tiles(s);  // also sets ntiles
   s->total = (size_t)off;
-  s->ntiles = (int)s->tiles_all.size();
   // state-check workgroups per instance: one per 16 Ki cells of a single grid, at most 512
   if (!batch) {
     const long long cells = s->h_inst[0].nx * s->h_inst[0].ny;

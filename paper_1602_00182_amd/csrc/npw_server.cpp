@@ -214,7 +214,7 @@ int rebuild_tiles(npw_server* s, Pool& pl) {
 int validate_request(const npw_server* s, const npw_params* p) {
   if (!p || p->abi_version != NPW_ABI_VERSION || p->dim != 1) return NPW_EINVAL;
   if (p->precision != s->precision) return NPW_EINVAL;
-  if (p->nx < 1 || p->nx > (1 << 30)) return NPW_EINVAL;
+  if (p->nx < 1 || (long long)(p->ncomp > 0 ? p->ncomp : 1) * p->nx > (1LL << 31) - (1LL << 16)) return NPW_EINVAL;
   if ((p->flux == NPW_ADVECTION || p->flux == NPW_BURGERS) && p->ncomp != 1) return NPW_EINVAL;
   if (p->flux == NPW_EULER && (p->ncomp != 3 || !(p->gamma > 1.0))) return NPW_EINVAL;
   if (p->flux < 0 || p->flux > 2) return NPW_EINVAL;

@@ -57,7 +57,7 @@ def test_params_struct_matches_header_defaults(L):
     {"cfl": 0.0}, {"cfl": float("nan")}, {"eps_weno": -1.0}, {"eps_m": 0.0}, {"x1": -2.0},
     {"abi_version": 99}, {"recon": 8}, {"recon": 9}, {"switch_mode": 9}, {"dt_fixed": -1.0},
     {"flux": 2, "ncomp": 3, "gamma": 1.0}, {"variables": 1}, {"flux": 2, "ncomp": 3, "variables": 2},
-    {"reserved": 1},
+    {"reserved": 1}, {"flux": 2, "ncomp": 3, "nx": 1 << 30}, {"nx": (1 << 31) - (1 << 16) + 1}, {"dim": 2, "nx": 64, "ny": 262141},
 ])
 def test_create_rejects_bad_parameters_before_allocating(L, bad):
     from paper_1602_00182_amd import binding as B

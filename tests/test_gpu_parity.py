@@ -367,3 +367,88 @@ def test_eno_euler_and_burgers(prec):
             # rounding may tip a tie-like comparison next to the jumps, moving a few cells by a
             # fraction of the jump (<= 0.9 here); 2e-4 mean allows about one such cell in 500.
             assert np.mean(np.abs(u - uo)) <= 2e-4
+
+
+# ---------------------------------------------------------------------------------------
+# largest grids: sampled interfaces against the oracle on local windows (advection, whose
+# Lax-Friedrichs alpha is the constant |a|, so a 13-cell periodic window around a cell gives the
+# same flux difference as the whole grid)
+# ---------------------------------------------------------------------------------------
+def _windows_from_device(u_dev, idx, n):
+    """13-cell periodic windows around the cells idx, copied out slice by slice (plain views)."""
+    out = []
+    for i in idx:
+        lo, hi = int(i) - 6, int(i) + 7
+        if lo < 0:
+            parts = [u_dev[n + lo:n], u_dev[0:hi]]
+        elif hi > n:
+            parts = [u_dev[lo:n], u_dev[0:hi - n]]
+        else:
+            parts = [u_dev[lo:hi]]
+        out.append(np.concatenate([p.cpu().numpy() for p in parts]).astype(np.float64))
+    return np.array(out)
+
+
+def _sample_indices(n, count, seed):
+    rng = np.random.default_rng(seed)
+    edge = np.array([0, 1, 2, 3, n - 4, n - 3, n - 2, n - 1, n // 2])
+    return np.unique(np.concatenate([edge, rng.integers(0, n, count)]))
+
+
+def _window_rhs(win, dx, recon=I.RBF_WENO5):
+    pb = O.Problem(nx=13, flux=I.ADVECTION, x0=0.0, x1=13 * dx, bc=I.PERIODIC, recon=recon)
+    L, _ = O.rhs(pb, win)
+    return L[6]
+
+
+def _big_advection_state(n, dtype, seed):
+    import torch
+    g = torch.Generator(device="cuda")
+    g.manual_seed(seed)
+    x = torch.arange(n, device="cuda", dtype=torch.float64) * (2.0 / n)
+    noise = torch.rand(n, device="cuda", dtype=torch.float64, generator=g)
+    spikes = (torch.rand(n, device="cuda", dtype=torch.float64, generator=g) < 0.05).to(torch.float64)
+    u = torch.sin(1000.0 * math.pi * x) + 0.2 * noise * spikes
+    return u.to(dtype)
+
+
+def test_large_grid_rhs_sampled_fp64():
+    """2^28 cells (2 GiB per state buffer), double bulk: sampled cells bit for bit."""
+    import torch
+    n = 1 << 28
+    _say(f"large grid rhs fp64 n={n}")
+    u = _big_advection_state(n, torch.float64, 31)
+    dx = 2.0 / n
+    w = I.Workload(name="big", nx=n, flux=I.ADVECTION, u0=np.zeros(1), T=1.0)
+    with B.Solver(u, **B.workload_params(w, B.FP64)) as s:
+        L = torch.empty_like(u)
+        s.rhs(L)
+        idx = _sample_indices(n, 1500, 32)
+        Lg = L[torch.as_tensor(idx, device="cuda")].cpu().numpy()
+    wins = _windows_from_device(u, idx, n)
+    del L, u
+    Lo = np.array([_window_rhs(wv, dx) for wv in wins])
+    assert np.array_equal(Lg, Lo)
+
+
+def test_largest_1d_grid_rhs_sampled_fp32():
+    """The largest 1D grid the library accepts (ncomp * nx = 2^31 - 2^16, the 32-bit index limit of
+    the 1D kernels with room for the last tile's halo), float bulk: sampled cells within 32 float
+    ulps of the flux scale over dx."""
+    import torch
+    n = (1 << 31) - (1 << 16)
+    _say(f"largest 1d grid rhs fp32 n={n}")
+    u = _big_advection_state(n, torch.float32, 41)
+    dx = 2.0 / n
+    w = I.Workload(name="max", nx=n, flux=I.ADVECTION, u0=np.zeros(1), T=1.0)
+    with B.Solver(u, **B.workload_params(w, B.FP32)) as s:
+        L = torch.empty_like(u)
+        s.rhs(L)
+        idx = _sample_indices(n, 1500, 42)
+        Lg = L[torch.as_tensor(idx, device="cuda")].cpu().numpy().astype(np.float64)
+    wins = _windows_from_device(u, idx, n)
+    del L, u
+    Lo = np.array([_window_rhs(wv, dx) for wv in wins])
+    umax = float(np.abs(wins).max())
+    tol = 32 * np.finfo(np.float32).eps * (2.0 * umax) / dx
+    assert np.max(np.abs(Lg - Lo)) <= tol
