@@ -1,0 +1,32 @@
+"""Host-side checks of bench.py: the one-GPU guard and the counter-summary lookup."""
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+
+def test_more_than_one_gpu_exits_with_a_message():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+
+
+def test_counter_traffic_requires_matching_kernel_and_source(tmp_path, monkeypatch):
+    import bench
+    h = bench.kernel_source_hash()
+    assert len(h) == 16
+    pdir = tmp_path / "profiles"
+    pdir.mkdir()
+    (pdir / "k_hbm_counters.txt").write_text(
+        f"# header\ntraffic kernel=stage1d_kernel<float,Burgers,1,128> source={h} bytes_per_launch=1234\n"
+        f"traffic kernel=other source=0000000000000000 bytes_per_launch=99\n")
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    monkeypatch.setattr(bench, "kernel_source_hash", lambda: h)
+    assert bench.counter_traffic("stage1d_kernel<float, Burgers, 1, 128>") == pytest.approx(1234.0)
+    assert bench.counter_traffic("other") is None  # summary taken with other kernel sources
+    assert bench.counter_traffic("stage1d_kernel<float, Burgers, 1, 256>") is None
