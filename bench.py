@@ -71,7 +71,7 @@ def counter_traffic(kernel: str):
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5, help="timed whole solves")
+    ap.add_argument("--steps", type=int, default=20, help="timed whole solves (p50/p99 latency over them)")
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", choices=["burgers", "euler2d", "euler_batch", "serving"], default="burgers")
     ap.add_argument("--precision", choices=["fp32", "fp64"], default="fp32")
