@@ -71,7 +71,9 @@ def counter_traffic(kernel: str):
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20, help="timed whole solves (p50/p99 latency over them)")
+    ap.add_argument("--steps", type=int, default=None,
+                    help="timed whole solves (default: 20 for burgers, so p50/p99 rest on 20 samples; 2 for "
+                         "euler_batch; 1 for euler2d, whose solve takes ~15 s)")
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", choices=["burgers", "euler2d", "euler_batch", "serving"], default="burgers")
     ap.add_argument("--precision", choices=["fp32", "fp64"], default="fp32")
@@ -284,6 +286,8 @@ def bench_serving(args, prec):
 
 def main():
     args = parse()
+    if args.steps is None:
+        args.steps = {"burgers": 20, "euler_batch": 2, "euler2d": 1}.get(args.workload, 1)
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print(f"bench.py: this build runs on one GPU only (asked for {max(args.gpus, world)} GPUs)", file=sys.stderr)
