@@ -540,7 +540,7 @@ const char* npweno_strerror(int code) {
   }
 }
 
-void npweno_default_params(npw_params* p) {
+static void npweno_default_params_impl(npw_params* p) {
   if (!p) return;
   std::memset(p, 0, sizeof *p);
   p->abi_version = NPW_ABI_VERSION;
@@ -658,17 +658,17 @@ static int create_common(const npw_params* p, int32_t count, const void* const* 
   return NPW_OK;
 }
 
-int npweno_create(const npw_params* p, const void* u0, int u0_on_device, void* hip_stream, npw_solver** out) {
+static int npweno_create_impl(const npw_params* p, const void* u0, int u0_on_device, void* hip_stream, npw_solver** out) {
   const void* one[1] = {u0};
   return create_common(p, 1, one, u0_on_device, hip_stream, false, out);
 }
 
-int npweno_create_batch(const npw_params* params, int32_t count, const void* const* u0, int on_device,
+static int npweno_create_batch_impl(const npw_params* params, int32_t count, const void* const* u0, int on_device,
                         void* hip_stream, npw_solver** out) {
   return create_common(params, count, u0, on_device, hip_stream, true, out);
 }
 
-int npweno_solve_batch(npw_solver* s, const double* t_final, int64_t max_steps, npw_stats* per_instance) {
+static int npweno_solve_batch_impl(npw_solver* s, const double* t_final, int64_t max_steps, npw_stats* per_instance) {
   if (!s || !t_final) return NPW_EINVAL;
   int rc = enter(s);
   if (rc) return rc;
@@ -682,7 +682,7 @@ int npweno_solve_batch(npw_solver* s, const double* t_final, int64_t max_steps, 
   return rc ? rc : rc2;
 }
 
-int npweno_read_instance(const npw_solver* cs, int32_t index, void* u_out, int out_on_device) {
+static int npweno_read_instance_impl(const npw_solver* cs, int32_t index, void* u_out, int out_on_device) {
   if (!cs || !u_out || index < 0 || index >= cs->ninst) return NPW_EINVAL;
   npw_solver* s = const_cast<npw_solver*>(cs);
   int rc = enter(s);
@@ -697,7 +697,7 @@ int npweno_read_instance(const npw_solver* cs, int32_t index, void* u_out, int o
   return leave(s);
 }
 
-int npweno_get_stats_instance(const npw_solver* cs, int32_t index, npw_stats* stats) {
+static int npweno_get_stats_instance_impl(const npw_solver* cs, int32_t index, npw_stats* stats) {
   if (!cs || !stats || index < 0 || index >= cs->ninst) return NPW_EINVAL;
   npw_solver* s = const_cast<npw_solver*>(cs);
   int rc = enter(s);
@@ -711,7 +711,7 @@ int npweno_get_stats_instance(const npw_solver* cs, int32_t index, npw_stats* st
 
 int npweno_instance_count(const npw_solver* s) { return s ? s->ninst : 0; }
 
-int npweno_launch_shape(const npw_solver* s, int32_t* block_1d, int32_t* tile_x, int32_t* tile_y,
+static int npweno_launch_shape_impl(const npw_solver* s, int32_t* block_1d, int32_t* tile_x, int32_t* tile_y,
                         int32_t* lds_shared) {
   if (!s) return NPW_EINVAL;
   static const int kTx[npw::k2dShapes] = {64, 62, 126, 64, 62, 126};
@@ -723,7 +723,7 @@ int npweno_launch_shape(const npw_solver* s, int32_t* block_1d, int32_t* tile_x,
   return NPW_OK;
 }
 
-int npweno_write(npw_solver* s, const void* u, int on_device, double t) {
+static int npweno_write_impl(npw_solver* s, const void* u, int on_device, double t) {
   if (!s || !u || !std::isfinite(t)) return NPW_EINVAL;
   int rc = enter(s);
   if (rc) return rc;
@@ -803,7 +803,7 @@ static int run_steps(npw_solver* s, const double* T, int64_t max_steps, int64_t*
   return first_err;
 }
 
-int npweno_step(npw_solver* s, double t_final, double* dt_taken) {
+static int npweno_step_impl(npw_solver* s, double t_final, double* dt_taken) {
   if (!s) return NPW_EINVAL;
   int rc = enter(s);
   if (rc) return rc;
@@ -815,7 +815,7 @@ int npweno_step(npw_solver* s, double t_final, double* dt_taken) {
   return rc ? rc : rc2;
 }
 
-int npweno_solve(npw_solver* s, double t_final, int64_t max_steps, npw_stats* stats) {
+static int npweno_solve_impl(npw_solver* s, double t_final, int64_t max_steps, npw_stats* stats) {
   if (!s) return NPW_EINVAL;
   int rc = enter(s);
   if (rc) return rc;
@@ -829,7 +829,7 @@ int npweno_solve(npw_solver* s, double t_final, int64_t max_steps, npw_stats* st
   return rc ? rc : rc2;
 }
 
-int npweno_rhs(npw_solver* s, void* L_out, int out_on_device) {
+static int npweno_rhs_impl(npw_solver* s, void* L_out, int out_on_device) {
   if (!s || !L_out) return NPW_EINVAL;
   if (s->sticky_err) return s->sticky_err;
   int rc = enter(s);
@@ -856,7 +856,7 @@ int npweno_rhs(npw_solver* s, void* L_out, int out_on_device) {
   return leave(s);
 }
 
-int npweno_read(const npw_solver* cs, void* u_out, int out_on_device) {
+static int npweno_read_impl(const npw_solver* cs, void* u_out, int out_on_device) {
   if (!cs || !u_out) return NPW_EINVAL;
   npw_solver* s = const_cast<npw_solver*>(cs);
   int rc = enter(s);
@@ -875,7 +875,7 @@ int npweno_read(const npw_solver* cs, void* u_out, int out_on_device) {
   return leave(s);
 }
 
-int npweno_get_stats(const npw_solver* cs, npw_stats* stats) {
+static int npweno_get_stats_impl(const npw_solver* cs, npw_stats* stats) {
   if (!cs || !stats) return NPW_EINVAL;
   npw_solver* s = const_cast<npw_solver*>(cs);
   int rc = enter(s);
@@ -888,10 +888,87 @@ int npweno_get_stats(const npw_solver* cs, npw_stats* stats) {
   return leave(s);
 }
 
-void npweno_destroy(npw_solver* s) {
+static void npweno_destroy_impl(npw_solver* s) {
   if (!s) return;
   (void)hipStreamSynchronize(s->stream);
   release(s);
 }
 
 }  // extern "C"
+
+// ---- C ABI entry points: no C++ exception crosses the boundary ------------------------
+// (std containers may throw std::bad_alloc; every entry point maps that to NPW_ENOMEM.)
+template <typename F>
+static int guarded(F&& f) noexcept {
+  try {
+    return f();
+  } catch (const std::bad_alloc&) {
+    return NPW_ENOMEM;
+  } catch (...) {
+    return NPW_EINVAL;
+  }
+}
+
+void npweno_default_params(npw_params* p) {
+  try {
+    npweno_default_params_impl(p);
+  } catch (...) {
+  }
+}
+
+int npweno_create(const npw_params* p, const void* u0, int u0_on_device, void* hip_stream, npw_solver** out) {
+  return guarded([&] { return npweno_create_impl(p, u0, u0_on_device, hip_stream, out); });
+}
+
+int npweno_create_batch(const npw_params* params, int32_t count, const void* const* u0, int on_device,
+                        void* hip_stream, npw_solver** out) {
+  return guarded([&] { return npweno_create_batch_impl(params, count, u0, on_device, hip_stream, out); });
+}
+
+int npweno_solve_batch(npw_solver* s, const double* t_final, int64_t max_steps, npw_stats* per_instance) {
+  return guarded([&] { return npweno_solve_batch_impl(s, t_final, max_steps, per_instance); });
+}
+
+int npweno_read_instance(const npw_solver* cs, int32_t index, void* u_out, int out_on_device) {
+  return guarded([&] { return npweno_read_instance_impl(cs, index, u_out, out_on_device); });
+}
+
+int npweno_get_stats_instance(const npw_solver* cs, int32_t index, npw_stats* stats) {
+  return guarded([&] { return npweno_get_stats_instance_impl(cs, index, stats); });
+}
+
+int npweno_launch_shape(const npw_solver* s, int32_t* block_1d, int32_t* tile_x, int32_t* tile_y,
+                        int32_t* lds_shared) {
+  return guarded([&] { return npweno_launch_shape_impl(s, block_1d, tile_x, tile_y, lds_shared); });
+}
+
+int npweno_write(npw_solver* s, const void* u, int on_device, double t) {
+  return guarded([&] { return npweno_write_impl(s, u, on_device, t); });
+}
+
+int npweno_step(npw_solver* s, double t_final, double* dt_taken) {
+  return guarded([&] { return npweno_step_impl(s, t_final, dt_taken); });
+}
+
+int npweno_solve(npw_solver* s, double t_final, int64_t max_steps, npw_stats* stats) {
+  return guarded([&] { return npweno_solve_impl(s, t_final, max_steps, stats); });
+}
+
+int npweno_rhs(npw_solver* s, void* L_out, int out_on_device) {
+  return guarded([&] { return npweno_rhs_impl(s, L_out, out_on_device); });
+}
+
+int npweno_read(const npw_solver* cs, void* u_out, int out_on_device) {
+  return guarded([&] { return npweno_read_impl(cs, u_out, out_on_device); });
+}
+
+int npweno_get_stats(const npw_solver* cs, npw_stats* stats) {
+  return guarded([&] { return npweno_get_stats_impl(cs, stats); });
+}
+
+void npweno_destroy(npw_solver* s) {
+  try {
+    npweno_destroy_impl(s);
+  } catch (...) {
+  }
+}

@@ -370,7 +370,7 @@ void destroy_server(npw_server* s) {
 
 extern "C" {
 
-int npw_server_create(size_t hbm_budget_bytes, int32_t max_slots, int32_t precision, void* hip_stream,
+static int npw_server_create_impl(size_t hbm_budget_bytes, int32_t max_slots, int32_t precision, void* hip_stream,
                       npw_server** out) {
   if (!out) return NPW_EINVAL;
   *out = nullptr;
@@ -423,7 +423,7 @@ int npw_server_create(size_t hbm_budget_bytes, int32_t max_slots, int32_t precis
   return NPW_OK;
 }
 
-int npw_server_submit(npw_server* s, const npw_params* p, const void* u0_host, double t_final, uint64_t* req_id) {
+static int npw_server_submit_impl(npw_server* s, const npw_params* p, const void* u0_host, double t_final, uint64_t* req_id) {
   if (!s || !p || !u0_host || !req_id || !std::isfinite(t_final) || t_final < 0.0) return NPW_EINVAL;
   int rc = validate_request(s, p);
   if (rc) return rc;
@@ -444,7 +444,7 @@ int npw_server_submit(npw_server* s, const npw_params* p, const void* u0_host, d
   return NPW_OK;
 }
 
-int npw_server_pump(npw_server* s, int32_t steps, int32_t* n_running, int32_t* n_queued) {
+static int npw_server_pump_impl(npw_server* s, int32_t steps, int32_t* n_running, int32_t* n_queued) {
   if (!s || steps < 1) return NPW_EINVAL;
   int rc = admit(s);
   if (rc) return rc;
@@ -487,7 +487,7 @@ int npw_server_pump(npw_server* s, int32_t steps, int32_t* n_running, int32_t* n
   return NPW_OK;
 }
 
-int npw_server_poll(npw_server* s, uint64_t req_id, void* u_out_host, npw_stats* stats) {
+static int npw_server_poll_impl(npw_server* s, uint64_t req_id, void* u_out_host, npw_stats* stats) {
   if (!s) return NPW_EINVAL;
   auto it = s->index.find(req_id);
   if (it == s->index.end()) return NPW_ENOTFOUND;
@@ -498,7 +498,7 @@ int npw_server_poll(npw_server* s, uint64_t req_id, void* u_out_host, npw_stats*
   return r.state == 3 ? (r.err ? r.err : NPW_ENONFINITE) : NPW_OK;
 }
 
-int npw_server_times(const npw_server* s, uint64_t req_id, double* t_submit, double* t_admit, double* t_done) {
+static int npw_server_times_impl(const npw_server* s, uint64_t req_id, double* t_submit, double* t_admit, double* t_done) {
   if (!s) return NPW_EINVAL;
   auto it = s->index.find(req_id);
   if (it == s->index.end()) return NPW_ENOTFOUND;
@@ -509,7 +509,7 @@ int npw_server_times(const npw_server* s, uint64_t req_id, double* t_submit, dou
   return r.state < 2 ? NPW_EBUSY : NPW_OK;
 }
 
-int npw_server_release(npw_server* s, uint64_t req_id) {
+static int npw_server_release_impl(npw_server* s, uint64_t req_id) {
   if (!s) return NPW_EINVAL;
   auto it = s->index.find(req_id);
   if (it == s->index.end()) return NPW_ENOTFOUND;
@@ -520,6 +520,51 @@ int npw_server_release(npw_server* s, uint64_t req_id) {
   return NPW_OK;
 }
 
-void npw_server_destroy(npw_server* s) { destroy_server(s); }
+static void npw_server_destroy_impl(npw_server* s) { destroy_server(s); }
 
 }  // extern "C"
+
+// ---- C ABI entry points: no C++ exception crosses the boundary ------------------------
+// (std containers may throw std::bad_alloc; every entry point maps that to NPW_ENOMEM.)
+template <typename F>
+static int guarded(F&& f) noexcept {
+  try {
+    return f();
+  } catch (const std::bad_alloc&) {
+    return NPW_ENOMEM;
+  } catch (...) {
+    return NPW_EINVAL;
+  }
+}
+
+int npw_server_create(size_t hbm_budget_bytes, int32_t max_slots, int32_t precision, void* hip_stream,
+                      npw_server** out) {
+  return guarded([&] { return npw_server_create_impl(hbm_budget_bytes, max_slots, precision, hip_stream, out); });
+}
+
+int npw_server_submit(npw_server* s, const npw_params* p, const void* u0_host, double t_final, uint64_t* req_id) {
+  return guarded([&] { return npw_server_submit_impl(s, p, u0_host, t_final, req_id); });
+}
+
+int npw_server_pump(npw_server* s, int32_t steps, int32_t* n_running, int32_t* n_queued) {
+  return guarded([&] { return npw_server_pump_impl(s, steps, n_running, n_queued); });
+}
+
+int npw_server_poll(npw_server* s, uint64_t req_id, void* u_out_host, npw_stats* stats) {
+  return guarded([&] { return npw_server_poll_impl(s, req_id, u_out_host, stats); });
+}
+
+int npw_server_times(const npw_server* s, uint64_t req_id, double* t_submit, double* t_admit, double* t_done) {
+  return guarded([&] { return npw_server_times_impl(s, req_id, t_submit, t_admit, t_done); });
+}
+
+int npw_server_release(npw_server* s, uint64_t req_id) {
+  return guarded([&] { return npw_server_release_impl(s, req_id); });
+}
+
+void npw_server_destroy(npw_server* s) {
+  try {
+    npw_server_destroy_impl(s);
+  } catch (...) {
+  }
+}
