@@ -1,4 +1,6 @@
-"""FP64 CPU oracle of the non-polynomial (MQ-RBF perturbed) WENO5 finite-volume scheme.
+"""FP64 CPU oracle of the non-polynomial (MQ-RBF perturbed) ENO/WENO finite-volume schemes:
+k = 3 (Table 3) and k = 2 (Table 2) in 1D and dimension by dimension in 2D, the two-dimensional
+k = 2 reconstruction of Section 6, and characteristic-wise Euler reconstruction.
 
 TEST INFRASTRUCTURE ONLY: the tests, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
 ``bench.py`` may import this package; the product library never does.  The arithmetic lives

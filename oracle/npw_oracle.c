@@ -1,7 +1,11 @@
 /*
  * npw_oracle.c -- plain, slow FP64 CPU oracle for the non-polynomial (multiquadric-RBF
- * perturbed) WENO5 finite-volume scheme of J. Guo and J.-H. Jung, "Non-polynomial ENO and
- * WENO finite volume methods for hyperbolic conservation laws" (arXiv:1602.00182).
+ * perturbed) ENO/WENO finite-volume schemes of J. Guo and J.-H. Jung, "Non-polynomial ENO and
+ * WENO finite volume methods for hyperbolic conservation laws" (arXiv:1602.00182): k = 3
+ * (Table 3) and k = 2 (Table 2) reconstructions with their shape parameters and the Section 4
+ * switch, ENO and WENO forms, the global Lax-Friedrichs flux and SSP-RK3 (Section 5.1), the
+ * dimension-by-dimension 2D form (Section 7), the two-dimensional k = 2 reconstruction of
+ * Section 6, and characteristic-wise Euler reconstruction.
  *
  * TEST INFRASTRUCTURE ONLY.  Nothing in the product path may link, load or call this file:
  * only the tests, the smoke check and the CPU-baseline leg of the benchmark use it.  It
