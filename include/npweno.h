@@ -174,7 +174,7 @@ int npweno_read_instance(const npw_solver* s, int32_t index, void* u_out, int ou
 int npweno_get_stats_instance(const npw_solver* s, int32_t index, npw_stats* stats);
 int npweno_instance_count(const npw_solver* s);
 /* Launch shape the solver uses for its stage kernel (picked at create by the autotuner, or set by
- * NPW_BLOCK / NPW_TILE2D): *block_1d = threads per workgroup of the 1D kernel (128, 256 or 512),
+ * NPW_BLOCK / NPW_TILE2D): *block_1d = threads per workgroup of the 1D kernel (64, 128, 256 or 512),
  * *tile_x, *tile_y = interior cells per workgroup of the 2D kernel (0 for a 1D solver), and
  * *lds_shared = 1 when the 2D kernel shares per-cell weight denominators through LDS, 0 when every
  * interface recomputes them (always 1 in 1D).  Any output pointer may be NULL.  Host-only;

@@ -28,6 +28,7 @@ static hipError_t launch_stage_bs(int flux, int ncomp, const StageArgs& a, hipSt
 
 hipError_t launch_stage_f32(int flux, int ncomp, int block, const StageArgs& a, hipStream_t s) {
   switch (block) {
+    case 64: return launch_stage_bs<64>(flux, ncomp, a, s);
     case 128: return launch_stage_bs<128>(flux, ncomp, a, s);
     case 256: return launch_stage_bs<256>(flux, ncomp, a, s);
     case 512: return launch_stage_bs<512>(flux, ncomp, a, s);

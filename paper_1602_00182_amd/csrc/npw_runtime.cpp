@@ -109,7 +109,7 @@ int env_block() {
   const char* s = std::getenv("NPW_BLOCK");
   if (!s) return 256;
   int b = std::atoi(s);
-  return (b == 128 || b == 256 || b == 512) ? b : 256;
+  return (b == 64 || b == 128 || b == 256 || b == 512) ? b : 256;
 }
 
 hipError_t launch_stage(const npw_solver* s, const StageArgs& a, hipStream_t st) {
@@ -268,7 +268,7 @@ int align_homes(npw_solver* s, int* gp_out) {
 int reset_instances(npw_solver* s, double t);
 
 // ---- tiles and block size --------------------------------------------------------------------
-constexpr int kBlocks[3] = {128, 256, 512};
+constexpr int kBlocks[4] = {64, 128, 256, 512};  // smallest first (max_tiles)
 
 size_t max_tiles(const npw_solver* s) {
   if (!s->batch) return 1;  // no table: tiles follow from the block index
@@ -330,7 +330,7 @@ std::string tune_key(const npw_solver* s) {
   int lg = 0;
   while ((1ll << (lg + 1)) <= cells) ++lg;
   std::ostringstream k;
-  k << "v2_d" << s->dim << "_f" << s->flux << "_m" << s->ncomp << "_p" << s->precision << "_n" << lg << "_i"
+  k << "v3_d" << s->dim << "_f" << s->flux << "_m" << s->ncomp << "_p" << s->precision << "_n" << lg << "_i"
     << (s->ninst > 1 ? 1 : 0) << (s->charw ? "_c" : "");
   return k.str();
 }
@@ -342,7 +342,7 @@ int tune_lookup(const std::string& key) {
   int found = -1;
   const bool two_d = key.find("_d2_") != std::string::npos;
   while (f >> k >> b)
-    if (k == key && (two_d ? (b >= 0 && b < npw::k2dShapes) : (b == 128 || b == 256 || b == 512))) found = b;
+    if (k == key && (two_d ? (b >= 0 && b < npw::k2dShapes) : (b == 64 || b == 128 || b == 256 || b == 512))) found = b;
   return found;
 }
 
@@ -362,7 +362,7 @@ void tune_store(const std::string& key, int block) {
 // candidate computes each cell with the same arithmetic, so the choice never changes results.
 // NPW_BLOCK / NPW_TILE2D fix the knob; NPW_AUTOTUNE=0 keeps the default.
 // Candidate c of the tuned knob: the 1D block size, or the 2D tile shape.
-int candidate_count(const npw_solver* s) { return s->dim == 1 ? 3 : npw::k2dShapes; }
+int candidate_count(const npw_solver* s) { return s->dim == 1 ? 4 : npw::k2dShapes; }
 int candidate_value(const npw_solver* s, int c) { return s->dim == 1 ? kBlocks[c] : c; }
 int apply_candidate(npw_solver* s, int v) {
   if (s->dim == 1) return set_block(s, v);

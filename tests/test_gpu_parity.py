@@ -62,6 +62,25 @@ def test_rhs_burgers_fp64(n, bc):
     assert np.array_equal(L, Lo)
 
 
+@pytest.mark.parametrize("block", ["64", "128", "256", "512"])
+def test_rhs_every_block_size_fp64(block, monkeypatch):
+    _say(f"rhs block={block}")
+    monkeypatch.setenv("NPW_BLOCK", block)
+    n = 3001
+    u0 = _random_burgers(n, 17)
+    for bc in (I.PERIODIC, I.TRANSMISSIVE):
+        w = I.Workload(name="r", nx=n, flux=I.BURGERS, u0=u0, T=1.0, bc=bc)
+        with _solver(w) as s:
+            assert s.launch_shape()["block"] == int(block)
+            L = s.rhs()
+            s.solve(w.T, max_steps=5)
+            u = s.read()
+        Lo, _ = O.rhs(_oracle_problem(w), u0)
+        assert np.array_equal(L, Lo)
+        uo, _, _ = O.solve(_oracle_problem(w), u0, w.T, max_steps=5)
+        assert np.array_equal(u, uo)
+
+
 @pytest.mark.parametrize("recon,sw", [(I.RBF_WENO5, I.SWITCH_MONOTONE), (I.RBF_WENO5, I.SWITCH_OFF),
                                       (I.WENO5_JS, I.SWITCH_MONOTONE), (I.RBF_ENO3, I.SWITCH_MONOTONE),
                                       (I.RBF_ENO3, I.SWITCH_OFF), (I.ENO3, I.SWITCH_MONOTONE)])

@@ -24,8 +24,8 @@ def test_autotuner_caches_and_block_size_never_changes_results(tmp_path, monkeyp
         s.solve(w.T, max_steps=40)
         tuned = s.read()
     lines = cache.read_text().split()
-    assert len(lines) == 2 and int(lines[1]) in (128, 256, 512)
-    for bs in ("128", "256", "512"):
+    assert len(lines) == 2 and int(lines[1]) in (64, 128, 256, 512)
+    for bs in ("64", "128", "256", "512"):
         monkeypatch.setenv("NPW_BLOCK", bs)
         with B.Solver(u32, **B.workload_params(w, B.FP32)) as s:
             s.solve(w.T, max_steps=40)
