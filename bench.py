@@ -85,6 +85,7 @@ def parse():
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a 256 MiB device copy (reference for HBM byte counters)")
     ap.add_argument("--serving-requests", type=int, default=200)
+    ap.add_argument("--pump-steps", type=int, default=64, help="RK steps per serving pump (admission granularity)")
     return ap.parse_args()
 
 
@@ -258,7 +259,7 @@ def bench_serving(args, prec):
         while pending and pending[0].arrival <= now:
             r = pending.pop(0)
             ids[r.rid] = srv.submit(np.asarray(r.work.u0, dt), r.work.T, **B.workload_params(r.work, prec))
-        srv.pump(16)
+        srv.pump(args.pump_steps)
     wall = time.perf_counter() - t0
     lat, nsteps = [], {}
     for r in trace:
@@ -281,7 +282,8 @@ def bench_serving(args, prec):
     wall1 = time.perf_counter() - t0
     return {"value": work / wall, "requests": nreq, "wall_s": wall, "latency_s": _percentiles(lat),
             "one_at_a_time": {"value": work / wall1, "wall_s": wall1, "latency_s": _percentiles(lat1)},
-            "offered_rate_req_s": 2000.0, "trace": f"first {nreq} requests of the seed-4 Poisson trace, N capped at 16384"}
+            "offered_rate_req_s": 2000.0, "pump_steps": args.pump_steps,
+            "trace": f"first {nreq} requests of the seed-4 Poisson trace, N capped at 16384"}
 
 
 def main():
