@@ -471,3 +471,27 @@ def test_largest_1d_grid_rhs_sampled_fp32():
     umax = float(np.abs(wins).max())
     tol = 32 * np.finfo(np.float32).eps * (2.0 * umax) / dx
     assert np.max(np.abs(Lg - Lo)) <= tol
+
+
+def test_solve_edge_semantics():
+    """max_steps = 0 takes no step; a target at or behind t takes none; steps split over calls
+    give the bits of one call; stats report t, steps and the oracle's alpha."""
+    _say("solve edge semantics")
+    w = I.burgers_noisy(n=997, seed=5)
+    with _solver(w) as s:
+        st = s.solve(w.T, max_steps=0)
+        assert st["nsteps"] == 0 and st["t"] == 0.0
+        st = s.solve(0.0)
+        assert st["nsteps"] == 0
+        s.solve(w.T, max_steps=7)
+        st = s.solve(w.T, max_steps=8)
+        assert st["nsteps"] == 15
+        t15 = st["t"]
+        assert s.solve(t15)["nsteps"] == 15  # already there
+        assert s.solve(t15 * 0.5)["nsteps"] == 15  # behind: nothing to do
+        u = s.read()
+        alpha = s.stats()["alpha"][0]
+    uo, to, no = O.solve(_oracle_problem(w), w.u0, w.T, max_steps=15)
+    assert no == 15 and to == t15
+    assert np.array_equal(u, uo)
+    assert alpha == O.alpha(_oracle_problem(w), uo)[0]
