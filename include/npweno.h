@@ -189,18 +189,23 @@ int npweno_launch_shape(const npw_solver* s, int32_t* block_1d, int32_t* tile_x,
  * Submitted requests wait in a FIFO queue; npw_server_pump admits the head of the queue as
  * soon as a slot and a large enough arena range are free, then advances every running request
  * by `steps` RK steps with one launch of the batched stage kernel per pool and stage
- * (their work overlaps on the device), and retires the finished ones.  A request's result is
+ * (their work overlaps on the device), and retires the finished ones.  A request that reaches
+ * its t_final within a pump stops there and idles for the rest of it.  A request's result is
  * bit-identical to solving it alone with npweno_create/npweno_solve in the same precision.
  * Requests never fail one another: a request that becomes non-finite or non-physical is
  * retired with its error and last good state. */
+/* max_slots in [1, 65536]; precision NPW_FP32 or NPW_FP64 for every request; hbm_budget_bytes at
+ * least 3 * 256 elements.  hip_stream is not used: requests enter and leave as host copies, and the
+ * server works on private streams of its own (pass NULL). */
 int npw_server_create(size_t hbm_budget_bytes, int32_t max_slots, int32_t precision, void* hip_stream,
                       npw_server** out);
 /* Queue a 1D solve to t_final (params->precision must equal the server's).  The library copies
  * u0_host.  NPW_EINVAL if the request could never fit in the arena. */
 int npw_server_submit(npw_server* srv, const npw_params* params, const void* u0_host, double t_final,
                       uint64_t* req_id);
-/* Admit, advance every running request by `steps` RK steps, retire.  Reports the number of
- * running and queued requests (either pointer may be NULL).  Synchronizes the device. */
+/* Admit, advance every running request by exactly `steps` (>= 1) RK steps (graphs of 256, 64,
+ * 16, 4 and 1 steps, largest first), retire.  Reports the number of running and queued requests
+ * (either pointer may be NULL).  Returns after the device work of the pump completed. */
 int npw_server_pump(npw_server* srv, int32_t steps, int32_t* n_running, int32_t* n_queued);
 /* NPW_EBUSY until the request finished; then copies its final state (the last good state and
  * the error code if it failed) and its stats. */

@@ -53,6 +53,7 @@ struct npw_solver {
   int sticky_err = 0;
   bool batch = false;              // created by npweno_create_batch
   std::vector<Tile> tiles_all;     // every tile of every instance
+  std::vector<Tile> tiles_live;    // host source of the last tile-table upload (kept until the next)
   std::vector<char> settled;       // per instance: error already handled
 };
 
@@ -61,7 +62,11 @@ constexpr long long kMaxElems1D = (1LL << 31) - (1LL << 16);  // largest 1D inst
 
 namespace {
 
-constexpr int kMaxGraphSteps = 256;  // steps per captured graph (3 stage kernels each)
+// Steps per captured graph (3 stage kernels each).  The host reads the instance table back after
+// every graph, which leaves the device idle for ~40 us; a single grid amortises that over 1024
+// steps, while a batch keeps 256 so that its tile table drops finished instances sooner.
+constexpr int kMaxGraphStepsSingle = 1024;
+constexpr int kMaxGraphStepsBatch = 256;
 
 #define HIP_TRY(expr)                          \
   do {                                         \
@@ -230,11 +235,16 @@ void clear_graphs(npw_solver* s) {
 // count, so they are re-captured when it changes.
 int set_tiles(npw_solver* s, const std::vector<char>& want, bool force) {
   if (!s->batch) return NPW_OK;  // a single grid derives its tiles from the block index
-  std::vector<Tile> t;
-  t.reserve(s->tiles_all.size());
+  size_t n = 0;
+  for (const Tile& x : s->tiles_all) n += want[x.inst] ? 1 : 0;
+  if (!force && 4 * n > 3 * (size_t)s->ntiles) return NPW_OK;
+  // the asynchronous copy reads tiles_live after this returns; the caller synchronizes the stream
+  // (pull) before the next call can refill it
+  std::vector<Tile>& t = s->tiles_live;
+  t.clear();
+  t.reserve(n);
   for (const Tile& x : s->tiles_all)
     if (want[x.inst]) t.push_back(x);
-  if (!force && 4 * t.size() > 3 * (size_t)s->ntiles) return NPW_OK;
   if (!t.empty())
     HIP_TRY(hipMemcpyAsync(s->d_tiles, t.data(), sizeof(Tile) * t.size(), hipMemcpyHostToDevice, s->stream));
   if ((int)t.size() != s->ntiles) clear_graphs(s);
@@ -769,6 +779,7 @@ static int run_steps(npw_solver* s, const double* T, int64_t max_steps, int64_t*
   int64_t launched = 0;
   int first_err = 0;
   std::vector<char> active(s->ninst, 0);
+  const int max_k = s->batch ? kMaxGraphStepsBatch : kMaxGraphStepsSingle;
   while (true) {
     int nactive = 0;
     double est = 0.0;
@@ -790,7 +801,7 @@ static int run_steps(npw_solver* s, const double* T, int64_t max_steps, int64_t*
         ++nactive;
         home = h.ctl[0].home;
         const double dt = h.ctl[1].dt;
-        est = std::max(est, dt > 0.0 ? rem / dt : (double)kMaxGraphSteps);
+        est = std::max(est, dt > 0.0 ? rem / dt : (double)max_k);
       }
     }
     if (taken) *taken = s->ninst == 1 ? (int64_t)(s->h_pin[0].ctl[0].n - n0) : launched;
@@ -800,7 +811,7 @@ static int run_steps(npw_solver* s, const double* T, int64_t max_steps, int64_t*
       rc = set_tiles(s, active, launched == 0);
       if (rc) return rc;
     }
-    int want = est < 1.0 ? 1 : (int)std::min((double)kMaxGraphSteps, std::ceil(est));
+    int want = est < 1.0 ? 1 : (int)std::min((double)max_k, std::ceil(est));
     if (max_steps >= 0) want = (int)std::min<int64_t>(want, max_steps - progress);
     int k = 1;
     while (k * 4 <= want) k *= 4;

@@ -114,7 +114,6 @@ struct npw_server {
   int max_slots = 0;
   int precision = NPW_FP32;
   size_t esize = 4;
-  hipStream_t user = nullptr;
   void* P0 = nullptr;
   void* P1 = nullptr;
   void* C = nullptr;
@@ -124,7 +123,6 @@ struct npw_server {
   std::vector<Request> reqs;      // every request ever submitted (by index)
   std::map<uint64_t, size_t> index;
   uint64_t next_id = 1;
-  hipEvent_t ev = nullptr;
 };
 
 namespace {
@@ -362,7 +360,6 @@ void destroy_server(npw_server* s) {
   if (s->P0) (void)hipFree(s->P0);
   if (s->P1) (void)hipFree(s->P1);
   if (s->C) (void)hipFree(s->C);
-  if (s->ev) (void)hipEventDestroy(s->ev);
   delete s;
 }
 
@@ -384,12 +381,11 @@ static int npw_server_create_impl(size_t hbm_budget_bytes, int32_t max_slots, in
   s->max_slots = max_slots;
   s->precision = precision;
   s->esize = esize;
-  s->user = reinterpret_cast<hipStream_t>(hip_stream);
+  (void)hip_stream;  // requests come and go as host copies; the pools run on private streams
   const size_t elems = hbm_budget_bytes / (3 * esize);
   s->arena.init(elems);
   bool ok = hipMalloc(&s->P0, elems * esize) == hipSuccess && hipMalloc(&s->P1, elems * esize) == hipSuccess &&
-            hipMalloc(&s->C, elems * esize) == hipSuccess &&
-            hipEventCreateWithFlags(&s->ev, hipEventDisableTiming) == hipSuccess;
+            hipMalloc(&s->C, elems * esize) == hipSuccess;
   const int ncomp[4] = {1, 1, 3, 3};
   for (int k = 0; k < 4 && ok; ++k) {
     Pool& pl = s->pools[k];
@@ -448,20 +444,23 @@ static int npw_server_pump_impl(npw_server* s, int32_t steps, int32_t* n_running
   if (!s || steps < 1) return NPW_EINVAL;
   int rc = admit(s);
   if (rc) return rc;
-  int k = 1;
-  while (k * 4 <= steps && k < 256) k *= 4;
-  if (k > 1 && (k & 1)) k = 1;
-  // launch every pool with running requests on its own stream, then wait for all of them
+  // launch every pool with running requests on its own stream, then wait for all of them; a
+  // pool advances by exactly `steps` RK steps as graphs of 256, 64, 16, 4 and 1 steps
   for (Pool& pl : s->pools) {
     if (pool_running(s, pl) == 0) continue;
     if (pl.dirty) {
       rc = rebuild_tiles(s, pl);
       if (rc) return rc;
     }
-    hipGraphExec_t g = pool_graph(s, pl, k, pl.par);
-    if (!g) return NPW_EHIP;
-    HIP_TRY(hipGraphLaunch(g, pl.stream));
-    if (k & 1) pl.par ^= 1;  // odd graphs leave u^n of the running requests in the other buffer
+    int left = steps;
+    for (int k = 256; k >= 1; k /= 4) {
+      for (; left >= k; left -= k) {
+        hipGraphExec_t g = pool_graph(s, pl, k, pl.par);
+        if (!g) return NPW_EHIP;
+        HIP_TRY(hipGraphLaunch(g, pl.stream));
+        if (k & 1) pl.par ^= 1;  // an odd graph leaves u^n of the running requests in the other buffer
+      }
+    }
   }
   for (Pool& pl : s->pools) {
     if (pool_running(s, pl) == 0) continue;

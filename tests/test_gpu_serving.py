@@ -86,3 +86,27 @@ def test_submit_validation():
         with pytest.raises(B.NpwError):
             big = np.zeros(200000)
             srv.submit(big, 1.0, nx=200000, flux=B.BURGERS, precision=B.FP32)  # can never fit
+
+
+def test_pump_advances_exactly_the_requested_steps():
+    """pump(7) is a 4-step graph and three 1-step graphs (each flips the ping-pong buffer);
+    requests admitted after odd pumps must start from the right buffer."""
+    _say("serving pump step count")
+    d = 2.0 ** -10  # binary dt, so t sums exactly to the step count
+    w = I.advection_sine(64, dt_fixed=d)
+    prm = B.workload_params(w)
+    with B.Server(1 << 20, max_slots=4, precision=B.FP64) as srv:
+        a = srv.submit(w.u0, 6 * d, **prm)
+        b = srv.submit(w.u0, 13 * d, **prm)
+        srv.pump(7)
+        assert srv.poll(a) is not None and srv.poll(b) is None
+        c = srv.submit(w.u0, 3 * d, **prm)  # admitted with u^n in the other buffer
+        srv.pump(5)
+        assert srv.poll(b) is None and srv.poll(c) is not None
+        srv.pump(1)
+        for rid, n in ((a, 6), (b, 13), (c, 3)):
+            out, st, rc = srv.poll(rid)
+            assert rc == B.OK and st["nsteps"] == n
+            with B.Solver(w.u0, **prm) as s:
+                s.solve(n * d)
+                assert np.array_equal(out, s.read()), rid
