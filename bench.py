@@ -188,6 +188,56 @@ def cpu_baseline(args, w, solver, u0_dev, prec):
     return base, err
 
 
+def cpu_baseline_batch(args, ws, bt, prec):
+    """The FP64 oracle on the host over the first instances of the same batch, each solved to its
+    T, instances spread over host threads (the oracle is plain C called through ctypes, which
+    releases the GIL).  Also the error of the GPU's final states on those instances."""
+    import concurrent.futures as cf
+
+    import oracle as O
+
+    from paper_1602_00182_amd import binding as B
+    threads = max(1, min(16, len(os.sched_getaffinity(0))))
+
+    def problem(w):
+        return O.Problem(nx=w.nx, flux=w.flux, ncomp=w.ncomp, bc=w.bc, x0=w.x0, x1=w.x1, gamma=w.gamma, cfl=w.cfl,
+                         eps_weno=w.eps_weno, eps_m=w.eps_m, recon=w.recon, switch_mode=w.switch_mode)
+
+    def init(w):
+        return np.asarray(w.u0, np.float32 if prec == B.FP32 else np.float64).astype(np.float64)
+
+    # cost model from one timed instance: steps grow with N, so work grows with N^2
+    a = time.perf_counter()
+    first = O.solve(problem(ws[0]), init(ws[0]), ws[0].T)
+    c = (time.perf_counter() - a) / float(ws[0].nx) ** 2
+    budget = args.cpu_seconds * threads
+    take, cost = 1, c * float(ws[0].nx) ** 2
+    while take < len(ws) and cost + c * float(ws[take].nx) ** 2 <= budget:
+        cost += c * float(ws[take].nx) ** 2
+        take += 1
+    sample = ws[1:take]
+    a = time.perf_counter()
+    with cf.ThreadPoolExecutor(max_workers=threads) as ex:
+        rest = list(ex.map(lambda w: O.solve(problem(w), init(w), w.T), sample))
+    el = time.perf_counter() - a
+    results = [first] + rest
+    work = sum(w.nx * 3.0 * r[2] for w, r in zip(ws[1:take], rest))
+    base = {"value": work / el if sample else None, "unit": "cell-updates/s", "cores": threads, "kind": "oracle",
+            "sample": f"instances 1..{take - 1} of the seed-3 batch (of {len(ws)}), each solved to T by the FP64 "
+                      f"oracle, {threads} instances at a time on host threads"}
+    l1 = linf = 0.0
+    cells = 0
+    for b, (w, r) in enumerate(zip(ws[:take], results)):
+        ug = bt.read(b).astype(np.float64)
+        d = np.abs(ug - r[0])
+        l1 += float(d.sum())
+        linf = max(linf, float(d.max()))
+        cells += d.size
+    err = {"vs": "FP64 oracle", "instances": take, "final_time": "T = 0.2 of each", "l1": l1 / cells,
+           "linf": linf}
+    return base, err
+
+
 def bench_batch(args, prec):
     import torch
 
@@ -231,8 +281,12 @@ def bench_batch(args, prec):
     max_steps = max(s["nsteps"] for s in stats)
     esize = 4 if prec == B.FP32 else 8
     achieved = ACCESSES_PER_CELL_STAGE * esize * 3 * total_cell_stages / gpu_s / 1e9
+    cb = err = None
+    if not args.no_cpu_baseline and args.max_rk_steps < 0:
+        cb, err = cpu_baseline_batch(args, ws, bt, prec)
     bt.close()
     return {"value": total_cell_stages / wall, "ms_per_step": 1e3 * wall / args.steps,
+            "cpu_baseline": cb, "error_vs_oracle": err,
             "latency_s": _percentiles(lat), "instances": len(ws), "cells": int(sum(w.nx for w in ws)),
             "max_rk_steps": max_steps,
             "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -335,6 +389,9 @@ def main():
                           "instances": res["instances"],
                           "cells": res["cells"], "max_rk_steps": res["max_rk_steps"]},
                "latency_s": res["latency_s"], "roofline": res["roofline"]}
+        if res["cpu_baseline"] is not None:
+            out["cpu_baseline"] = res["cpu_baseline"]
+            out["error_vs_oracle"] = res["error_vs_oracle"]
     else:
         res = bench_serving(args, prec)
         out = {"metric": METRIC,

@@ -30,3 +30,29 @@ def test_counter_traffic_requires_matching_kernel_and_source(tmp_path, monkeypat
     assert bench.counter_traffic("stage1d_kernel<float, Burgers, 1, 128>") == pytest.approx(1234.0)
     assert bench.counter_traffic("other") is None  # summary taken with other kernel sources
     assert bench.counter_traffic("stage1d_kernel<float, Burgers, 1, 256>") is None
+
+
+def test_batch_cpu_baseline_threads_and_error(monkeypatch):
+    """The batch baseline solves a prefix of the batch on host threads and measures the GPU's
+    final states against the oracle's (here a stand-in batch that returns the oracle's own)."""
+    import types
+
+    import numpy as np
+
+    import bench
+    import oracle as O
+    from paper_1602_00182_amd import inputs as I
+    ws = I.euler_riemann_batch(count=6, seed=3)
+    ws = [w.with_(T=0.02) for w in ws]
+
+    class Exact:
+        def read(self, b):
+            w = ws[b]
+            pb = O.Problem(nx=w.nx, flux=w.flux, ncomp=w.ncomp, bc=w.bc, x0=w.x0, x1=w.x1, gamma=w.gamma, cfl=w.cfl)
+            return O.solve(pb, w.u0, w.T)[0]
+
+    args = types.SimpleNamespace(cpu_seconds=60.0)
+    base, err = bench.cpu_baseline_batch(args, ws, Exact(), 0)  # 0 = FP64 bulk
+    assert base["kind"] == "oracle" and base["cores"] >= 1 and base["value"] > 0
+    assert err["instances"] == len(ws)
+    assert err["l1"] == 0.0 and err["linf"] == 0.0

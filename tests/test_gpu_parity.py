@@ -133,6 +133,21 @@ def test_burgers_noisy_steps_fp64():
     assert np.array_equal(u, uo)
 
 
+def test_long_solve_across_graph_sizes_fp64():
+    """More than 1024 steps through the shock, interrupted by max_steps: the solve replays
+    graphs of 1024, 256, 64, 16, 4 and 1 steps and must still follow the oracle bit for bit."""
+    _say("burgers N384 long solve fp64")
+    w = I.burgers_noisy(n=384, seed=2, T=4.0)  # 1574 steps
+    with _solver(w) as s:
+        st1 = s.solve(w.T, max_steps=1100)
+        assert st1["nsteps"] == 1100
+        st = s.solve(w.T)
+        u = s.read()
+    uo, to, no = O.solve(_oracle_problem(w), w.u0, w.T)
+    assert st["nsteps"] == no > 1100 and st["t"] == to
+    assert np.array_equal(u, uo)
+
+
 def test_sod_fp64():
     _say("sod N600 fp64")
     w = I.sod(600, T=0.2, cfl=0.5)
