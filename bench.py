@@ -9,7 +9,11 @@ value = cells * 3 stages * RK steps * solves / wall seconds (cell-updates per RK
 
 Other workloads (--workload): euler2d (2048^2 four-quadrant 2D Euler to T = 0.25), euler_batch
 (4096 Riemann problems, N in [256, 4096], to T = 0.2), serving (a Poisson trace through the
-continuous-batching loop, compared with one solve at a time).
+continuous-batching loop, compared with one solve at a time), advection (sin(pi x) at N = 65536
+to T = 0.5) and advection2d (sin(2 pi (x + y)) on 2048^2 to T = 0.25), the paper's smooth test
+problems at the headline's sizes, on which the k = 2 and Section 6 reconstructions are defined
+everywhere (their shape parameter is singular where a solution with non-zero curvature crosses
+zero).  --recon and --variables pick the reconstruction.
 
 Prints one JSON line.  Only one GPU: --gpus N > 1 exits with a message.
 """
@@ -37,6 +41,29 @@ METRIC = "cell-updates/s per RK stage at stated L1 err vs FP64 oracle; p50/p99 s
 
 KERNEL_SOURCES = ("npw_device.h", "npw_internal.h", "npw_kernels.h", "npw_kernels2d.h", "npw_kernels_f32.hip",
                   "npw_kernels_f64.hip")
+
+# reconstruction codes of include/npweno.h by name
+RECONS = {"rbf_weno5": 0, "weno5_js": 1, "rbf_eno3": 2, "eno3": 3, "rbf_weno3": 4, "weno3_js": 5, "rbf_eno2": 6,
+          "eno2": 7, "rbf_eno2_2d": 8}
+FLUX_NAMES = {0: "Advection", 1: "Burgers", 2: "Euler"}
+
+
+def kernel_label(w, prec, shape, batched=False):
+    """Name of the stage-kernel instantiation a workload runs (the key of the counter summaries):
+    template arguments as in the source, plus k2 (compiled with the k = 2 code) and char
+    (characteristic-wise) when they apply."""
+    R = "float" if prec == 1 else "double"
+    extra = (", k2" if w.recon >= 4 else "") + (", char" if w.variables == 1 else "")
+    if w.dim == 1:
+        lab = f"stage1d_kernel<{R}, {FLUX_NAMES[w.flux]}, {w.ncomp}, {shape['block']}{extra}>"
+        return lab + " (batched)" if batched else lab
+    share = "" if shape["lds_shared"] else ", recompute"
+    return f"stage2d_kernel<{R}, {FLUX_NAMES[w.flux]}, {w.ncomp}, {shape['tile_x']}, {shape['tile_y']}{share}{extra}>"
+
+
+def scheme_of(w):
+    name = {v: k for k, v in RECONS.items()}[w.recon]
+    return name + (", characteristic" if w.variables == 1 else "") + (", switch off" if w.switch_mode == 1 else "")
 
 
 def kernel_source_hash() -> str:
@@ -75,7 +102,8 @@ def parse():
                     help="timed whole solves (default: 20 for burgers, so p50/p99 rest on 20 samples; 2 for "
                          "euler_batch; 1 for euler2d, whose solve takes ~15 s)")
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", choices=["burgers", "euler2d", "euler_batch", "serving"], default="burgers")
+    ap.add_argument("--workload", choices=["burgers", "advection", "euler2d", "advection2d", "euler_batch", "serving"],
+                    default="burgers")
     ap.add_argument("--precision", choices=["fp32", "fp64"], default="fp32")
     ap.add_argument("--n", type=int, default=None, help="override the grid size")
     ap.add_argument("--max-rk-steps", type=int, default=-1,
@@ -84,6 +112,10 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a 256 MiB device copy (reference for HBM byte counters)")
+    ap.add_argument("--recon", choices=sorted(RECONS), default=None,
+                    help="reconstruction (default: each workload's own, rbf_weno5 with the monotone switch)")
+    ap.add_argument("--variables", choices=["componentwise", "characteristic"], default="componentwise",
+                    help="Euler reconstruction variables (euler_batch and euler2d)")
     ap.add_argument("--serving-requests", type=int, default=200)
     ap.add_argument("--pump-steps", type=int, default=64, help="RK steps per serving pump (admission granularity)")
     return ap.parse_args()
@@ -122,6 +154,18 @@ def _time_solves(solver, reset, T, steps, warmup, max_rk, stream):
     return wall, gpu_s, lat, rk
 
 
+def apply_scheme(args, w):
+    """The workload with the reconstruction and variables asked for on the command line."""
+    kw = {}
+    if args.recon is not None:
+        kw["recon"] = RECONS[args.recon]
+    if args.variables == "characteristic":
+        if w.flux != 2:
+            raise SystemExit("bench.py: --variables characteristic needs an Euler workload")
+        kw["variables"] = 1
+    return w.with_(**kw) if kw else w
+
+
 def bench_single(args, w, prec):
     """A single grid (1D or 2D) solved from its initial state `steps` times."""
     import torch
@@ -132,12 +176,7 @@ def bench_single(args, w, prec):
     stream = torch.cuda.Stream()
     solver = B.Solver(u0_dev, stream=stream.cuda_stream, **B.workload_params(w, prec))
     shape = solver.launch_shape()
-    R = "float" if prec == B.FP32 else "double"
-    if w.dim == 1:
-        label = f"stage1d_kernel<{R}, Burgers, 1, {shape['block']}>"
-    else:
-        share = "" if shape["lds_shared"] else ", recompute"
-        label = f"stage2d_kernel<{R}, Euler, 4, {shape['tile_x']}, {shape['tile_y']}{share}>"
+    label = kernel_label(w, prec, shape)
     wall, gpu_s, lat, rk = _time_solves(solver, lambda: solver.write(u0_dev, 0.0), w.T, args.steps, args.warmup,
                                         args.max_rk_steps, stream)
     ncell = w.ncell
@@ -168,7 +207,8 @@ def cpu_baseline(args, w, solver, u0_dev, prec):
     from paper_1602_00182_amd import binding as B
     pb = O.Problem(nx=w.nx, ny=w.ny, dim=w.dim, flux=w.flux, ncomp=w.ncomp, bc=w.bc, x0=w.x0, x1=w.x1,
                    y0=w.y0, y1=w.y1, speed_x=w.speed_x, speed_y=w.speed_y, gamma=w.gamma, cfl=w.cfl,
-                   eps_weno=w.eps_weno, eps_m=w.eps_m, recon=w.recon, switch_mode=w.switch_mode)
+                   eps_weno=w.eps_weno, eps_m=w.eps_m, recon=w.recon, switch_mode=w.switch_mode,
+                   charwise=1 if w.variables == 1 else 0)
     u_ref = np.asarray(w.u0, np.float32 if prec == B.FP32 else np.float64).astype(np.float64)
     a = time.perf_counter()
     u1, t1, _ = O.step(pb, u_ref, w.T)
@@ -201,7 +241,8 @@ def cpu_baseline_batch(args, ws, bt, prec):
 
     def problem(w):
         return O.Problem(nx=w.nx, flux=w.flux, ncomp=w.ncomp, bc=w.bc, x0=w.x0, x1=w.x1, gamma=w.gamma, cfl=w.cfl,
-                         eps_weno=w.eps_weno, eps_m=w.eps_m, recon=w.recon, switch_mode=w.switch_mode)
+                         eps_weno=w.eps_weno, eps_m=w.eps_m, recon=w.recon, switch_mode=w.switch_mode,
+                         charwise=1 if w.variables == 1 else 0)
 
     def init(w):
         return np.asarray(w.u0, np.float32 if prec == B.FP32 else np.float64).astype(np.float64)
@@ -243,7 +284,7 @@ def bench_batch(args, prec):
 
     from paper_1602_00182_amd import binding as B
     from paper_1602_00182_amd import inputs as I
-    ws = I.euler_riemann_batch(count=4096 if args.n is None else args.n, seed=3)
+    ws = [apply_scheme(args, w) for w in I.euler_riemann_batch(count=4096 if args.n is None else args.n, seed=3)]
     dt = np.float32 if prec == B.FP32 else np.float64
     states = [np.asarray(w.u0, dt) for w in ws]
     stream = torch.cuda.Stream()
@@ -284,14 +325,15 @@ def bench_batch(args, prec):
     cb = err = None
     if not args.no_cpu_baseline and args.max_rk_steps < 0:
         cb, err = cpu_baseline_batch(args, ws, bt, prec)
+    shape = bt.launch_shape()
     bt.close()
     return {"value": total_cell_stages / wall, "ms_per_step": 1e3 * wall / args.steps,
-            "cpu_baseline": cb, "error_vs_oracle": err,
+            "cpu_baseline": cb, "error_vs_oracle": err, "scheme": scheme_of(ws[0]),
             "latency_s": _percentiles(lat), "instances": len(ws), "cells": int(sum(w.nx for w in ws)),
             "max_rk_steps": max_steps,
             "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                          "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                         "kernel": "stage1d_kernel<float, Euler, 3> (batched)",
+                         "kernel": kernel_label(ws[0], prec, shape, batched=True),
                          "note": "bytes of all instances / GPU time of the timed region"}}
 
 
@@ -343,7 +385,8 @@ def bench_serving(args, prec):
 def main():
     args = parse()
     if args.steps is None:
-        args.steps = {"burgers": 20, "euler_batch": 2, "euler2d": 1}.get(args.workload, 1)
+        args.steps = {"burgers": 20, "advection": 20, "euler_batch": 2, "euler2d": 1, "advection2d": 3}.get(
+            args.workload, 1)
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print(f"bench.py: this build runs on one GPU only (asked for {max(args.gpus, world)} GPUs)", file=sys.stderr)
@@ -359,17 +402,27 @@ def main():
             "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": dname,
             "data": "synthetic (seeded)"}
 
-    if args.workload in ("burgers", "euler2d"):
-        if args.workload == "burgers":
-            w = I.burgers_noisy(n=args.n or 65536, seed=2)
-            desc = ("1D Burgers N=65536 periodic, u0 = 0.5 + sin(pi x) + seeded noise 1e-3, RBF-WENO5 with the "
-                    "monotone switch, global LF, SSP-RK3 CFL 0.5 to T=1.5/pi")
+    if args.workload in ("burgers", "advection", "euler2d", "advection2d"):
+        if args.workload == "advection":
+            w = apply_scheme(args, I.advection_sine(n=args.n or 65536, T=0.5))
+            desc = (f"1D linear advection N={w.nx} periodic, u0 = sin(pi x) (Table 5's problem at the headline's "
+                    f"size), {scheme_of(w)}, global LF, SSP-RK3 CFL 0.5 to T=0.5")
+        elif args.workload == "advection2d":
+            w = apply_scheme(args, I.advection2d_sine(n=args.n or 2048))
+            desc = (f"2D linear advection v_t + v_x + v_y = 0 on {w.nx}^2 cells of [0,1]^2, periodic, "
+                    f"v0 = sin(2 pi (x + y)) (Section 6's problem), {scheme_of(w)}, CFL 0.4 to T=0.25")
+        elif args.workload == "burgers":
+            w = apply_scheme(args, I.burgers_noisy(n=args.n or 65536, seed=2))
+            desc = (f"1D Burgers N={w.nx} periodic, u0 = 0.5 + sin(pi x) + seeded noise 1e-3, {scheme_of(w)}, "
+                    "global LF, SSP-RK3 CFL 0.5 to T=1.5/pi")
         else:
-            w = I.euler2d_quadrants(n=args.n or 2048)
-            desc = "2D Euler 2048^2 four-quadrant Riemann data, dimension by dimension, CFL 0.4 to T=0.25"
+            w = apply_scheme(args, I.euler2d_quadrants(n=args.n or 2048))
+            desc = (f"2D Euler {w.nx}^2 four-quadrant Riemann data, {scheme_of(w)}, dimension by dimension, "
+                    "CFL 0.4 to T=0.25")
         res, solver, u0_dev = bench_single(args, w, prec)
         out = {"metric": METRIC, "value": res["value"], **base, "ms_per_step": res["ms_per_step"],
-               "config": {"workload": w.name, "description": desc, "cells": w.ncell, "T": w.T, "cfl": w.cfl,
+               "config": {"workload": w.name, "description": desc, "scheme": scheme_of(w), "cells": w.ncell,
+                          "T": w.T, "cfl": w.cfl,
                           "rk_steps_per_solve": res["rk_steps_per_solve"], "eta_precision": "f64",
                           "launch_shape": res["launch_shape"]},
                "latency_s": res["latency_s"], "roofline": res["roofline"]}
@@ -386,6 +439,7 @@ def main():
                "value": res["value"], **base, "ms_per_step": res["ms_per_step"],
                "config": {"workload": "euler_riemann_batch_4096",
                           "description": "4096 1D Euler Riemann problems, N in [256,4096], CFL 0.5 to T=0.2",
+                          "scheme": res["scheme"],
                           "instances": res["instances"],
                           "cells": res["cells"], "max_rk_steps": res["max_rk_steps"]},
                "latency_s": res["latency_s"], "roofline": res["roofline"]}

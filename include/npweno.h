@@ -177,7 +177,7 @@ int npweno_instance_count(const npw_solver* s);
  * NPW_BLOCK / NPW_TILE2D): *block_1d = threads per workgroup of the 1D kernel (64, 128, 256 or 512),
  * *tile_x, *tile_y = interior cells per workgroup of the 2D kernel (0 for a 1D solver), and
  * *lds_shared = 1 when the 2D kernel shares per-cell weight denominators through LDS, 0 when every
- * interface recomputes them (always 1 in 1D).  Any output pointer may be NULL.  Host-only;
+ * interface recomputes them (always 0 for characteristic-wise 2D, always 1 in 1D).  Any output pointer may be NULL.  Host-only;
  * returns NPW_EINVAL for a NULL solver. */
 int npweno_launch_shape(const npw_solver* s, int32_t* block_1d, int32_t* tile_x, int32_t* tile_y,
                         int32_t* lds_shared);

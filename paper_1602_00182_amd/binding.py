@@ -284,6 +284,8 @@ class Batch:
         _check(lib().npweno_get_stats_instance(self.h, b, ctypes.byref(st)), "npweno_get_stats_instance")
         return st.as_dict()
 
+    launch_shape = Solver.launch_shape
+
     def close(self):
         if getattr(self, "h", None):
             lib().npweno_destroy(self.h)

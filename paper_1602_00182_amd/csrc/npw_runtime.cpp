@@ -740,7 +740,8 @@ static int npweno_launch_shape_impl(const npw_solver* s, int32_t* block_1d, int3
   if (block_1d) *block_1d = s->block;
   if (tile_x) *tile_x = s->dim == 2 ? kTx[s->shape2d] : 0;
   if (tile_y) *tile_y = s->dim == 2 ? kTy[s->shape2d] : 0;
-  if (lds_shared) *lds_shared = s->dim == 2 ? (s->shape2d < 3 ? 1 : 0) : 1;
+  // characteristic-wise 2D reconstruction works per interface and shares nothing per cell
+  if (lds_shared) *lds_shared = s->dim == 2 ? (s->shape2d < 3 && !s->charw ? 1 : 0) : 1;
   return NPW_OK;
 }
 

@@ -180,6 +180,18 @@ def euler2d_quadrants(n: int = 2048, seed: int = 5, T: float = 0.25, cfl: float 
                     gamma=gamma, meta={"states": states})
 
 
+def advection2d_sine(n: int = 2048, T: float = 0.25, cfl: float = 0.4, **kw) -> Workload:
+    """Section 6's test problem: v_t + v_x + v_y = 0 on [0,1]^2, periodic, v0 = sin(2 pi (x + y)).
+    Exact cell averages: sin(2 pi (x_i + y_j)) * s^2 with s = sin(pi h) / (pi h), because the
+    average of exp(2 pi i x) over a cell is exp(2 pi i x_i) s."""
+    h = 1.0 / n
+    xc = cell_centers(n, 0.0, 1.0)
+    s = math.sin(math.pi * h) / (math.pi * h)
+    u0 = np.sin(2.0 * math.pi * (xc[None, :] + xc[:, None])) * (s * s)  # [j, i]
+    return Workload(name=f"advection2d_sine_{n}", nx=n, ny=n, dim=2, flux=ADVECTION, u0=u0.reshape(-1), T=T,
+                    cfl=cfl, x0=0.0, x1=1.0, y0=0.0, y1=1.0, speed_x=1.0, speed_y=1.0, **kw)
+
+
 def smooth_plus_step(n: int, kind: int, rng: np.random.Generator, gamma: float = 1.4) -> np.ndarray:
     """Serving-trace initial data: A sin(pi k x + phi) + B H(x - xs) on [-1, 1] for scalars; Euler
     gets rho = 1 + 0.3 (same shape), p = 1 + 0.3 (same shape), u = 0.2 sin(pi x)."""
