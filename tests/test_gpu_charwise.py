@@ -84,6 +84,24 @@ def test_2d_fp64(recon):
     assert np.array_equal(u, uo)
 
 
+@pytest.mark.parametrize("shape", range(6))
+def test_2d_every_launch_shape_fp64(shape, monkeypatch):
+    """Every 2D tile shape gives the oracle's bits; the characteristic kernel shares nothing
+    per cell, so it reports lds_shared = 0 whatever the shape."""
+    _say(f"charwise 2d shape={shape}")
+    monkeypatch.setenv("NPW_TILE2D", str(shape))
+    base = I.euler2d_quadrants(n=70, seed=5)
+    w = base.with_(ny=53, u0=base.u0.reshape(4, 70, 70)[:, :53, :].reshape(-1), variables=I.CHARACTERISTIC)
+    with B.Solver(w.u0, **B.workload_params(w, B.FP64)) as s:
+        ls = s.launch_shape()
+        assert (ls["tile_x"], ls["tile_y"]) == [(64, 8), (62, 8), (126, 4)][shape % 3]
+        assert ls["lds_shared"] == 0
+        s.solve(w.T, max_steps=3)
+        u = s.read()
+    uo, _, _ = O.solve(_problem(w), w.u0, w.T, max_steps=3)
+    assert np.array_equal(u, uo)
+
+
 def test_fp32_smooth_density_wave():
     _say("charwise fp32 smooth")
     n = 512
