@@ -702,9 +702,11 @@ __device__ __forceinline__ R wave_max_nonneg(R v) {
 
 // Float-bulk single grids tag every spread alpha entry with the stage that wrote it:
 // entry = (stage sequence << 32) | float bits of alpha, the sequence of RK stage k of step n being
-// 3n + k and that of the state check of u^n being 3n.  Newer tags win the atomicMax, and a reader
-// keeps only the entries carrying the sequence it expects, so no kernel has to clear a slot (the
-// state check clears all of them whenever the state is replaced).
+// 3 (n - seq_base) + k and that of the state check of u^n being 3 (n - seq_base).  Newer tags win
+// the atomicMax, and a reader keeps only the entries carrying the sequence it expects, so no
+// kernel has to clear a slot (the state check clears all of them whenever the state is replaced).
+// The host keeps the sequence far below 2^32 by moving seq_base forward and re-running the state
+// check, which clears the slots and re-seeds slot 0.
 __device__ __forceinline__ unsigned long long spread_tag(long long seq, float a) {
   return ((unsigned long long)(unsigned)seq << 32) | (unsigned long long)__float_as_uint(a);
 }
@@ -719,7 +721,7 @@ __device__ __forceinline__ unsigned long long spread_reduce(unsigned long long e
 }
 // This lane's entry of (slot, dir).
 __device__ __forceinline__ unsigned long long spread_entry(const unsigned long long* spread, int slot, int dir) {
-  return spread[((slot * 2 + dir) * kSpread + (threadIdx.x & 63)) * kSpreadStride];
+  return spread[((slot * 2 + dir) * kSpread + (threadIdx.x & (kSpread - 1))) * kSpreadStride];
 }
 
 

@@ -28,6 +28,9 @@ struct InstDev {
   double inv_dx, inv_dy;  // float bulk multiplies by these instead of dividing
   double speed_x, speed_y, gamma, eps_weno, eps_m;
   int bc, recon, sw, dim;
+  // float-bulk single grids: spread alpha entries are tagged with 3 (n - seq_base) + stage, and
+  // the host moves seq_base forward (re-seeding the entries) long before that nears 2^32
+  long long seq_base;
   // dynamic
   Ctl ctl[3];
   // Lax-Friedrichs alpha slots (bit patterns of non-negative doubles, combined with atomicMax):
@@ -77,6 +80,8 @@ struct StageArgs {
 
 constexpr int kSpread = 64;
 constexpr int kSpreadStride = 16;  // 128 bytes between entries
+static_assert(kSpread >= 1 && kSpread <= 64 && (kSpread & (kSpread - 1)) == 0,
+              "a wave reads one spread entry per lane (lane & (kSpread - 1))");
 constexpr int kSpreadWords = 3 * 2 * kSpread * kSpreadStride;
 
 // Launchers implemented in the kernel translation units (one per bulk precision).

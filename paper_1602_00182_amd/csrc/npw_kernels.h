@@ -75,11 +75,12 @@ __device__ __forceinline__ void stage1d_tile(const StageArgs& a, const Tile tile
   const unsigned long long sp_e = sp ? spread_entry(sp, slot_in, 0) : 0ull;
   const int err = I->err;
   const Ctl c0 = I->ctl[0], c1 = I->ctl[1], c2 = I->ctl[2];
+  const long long seq_base = I->seq_base;
   unsigned long long alpha_bits;
   if (sp) {
     if constexpr (kTag) {
       const long long n_in = stage <= 1 ? c0.n : (stage == 2 ? c1.n : c2.n);
-      alpha_bits = spread_reduce_tagged(sp_e, 3 * n_in + slot_in);
+      alpha_bits = spread_reduce_tagged(sp_e, 3 * (n_in - seq_base) + slot_in);
     } else {
       alpha_bits = spread_reduce(sp_e);
     }
@@ -91,7 +92,7 @@ __device__ __forceinline__ void stage1d_tile(const StageArgs& a, const Tile tile
   // zero an alpha slot before the kernel that accumulates into it runs (tagged slots need not be)
   auto zero_slot = [&](int slot) {
     if (sp) {
-      if (!kTag && lead_wave) {
+      if (!kTag && lead_wave && tid < kSpread) {
         sp[((slot * 2 + 0) * kSpread + tid) * kSpreadStride] = 0ull;
         sp[((slot * 2 + 1) * kSpread + tid) * kSpreadStride] = 0ull;
       }
@@ -312,7 +313,7 @@ __device__ __forceinline__ void stage1d_tile(const StageArgs& a, const Tile tile
     } else {
       if (sp && kTag)
         atomicMax(&sp[((slot * 2 + 0) * kSpread + blockIdx.x % kSpread) * kSpreadStride],
-                  spread_tag(3 * n + stage, float(bits_to_double(m))));
+                  spread_tag(3 * (n - seq_base) + stage, float(bits_to_double(m))));
       else
         atomicMax(sp ? &sp[((slot * 2 + 0) * kSpread + blockIdx.x % kSpread) * kSpreadStride] : &I->alpha[slot][0], m);
     }
@@ -438,8 +439,8 @@ static __global__ __launch_bounds__(64) void check_final_kernel(InstDev* inst, i
   for (int c = 0; c < 4; ++c) I->mass[c] = c < ncomp ? tot[c] * area : 0.0;
   I->alpha[0][0] = mx;
   I->alpha[0][1] = my;
-  if (spread) {  // the state of step n opens sequence 3n (see spread_tag)
-    const long long seq = 3 * I->ctl[0].n;
+  if (spread) {  // the state of step n opens sequence 3 (n - seq_base) (see spread_tag)
+    const long long seq = 3 * (I->ctl[0].n - I->seq_base);
     spread[(0 * kSpread + 0) * kSpreadStride] = tagged ? spread_tag(seq, float(bits_to_double(mx))) : mx;
     spread[(1 * kSpread + 0) * kSpreadStride] = tagged ? spread_tag(seq, float(bits_to_double(my))) : my;
   }

@@ -87,7 +87,7 @@ __global__ __launch_bounds__(256) void stage2d_kernel(StageArgs a) {
   unsigned long long ax_bits, ay_bits;
   if (sp) {
     if constexpr (kTag) {
-      const long long n_in = stage <= 1 ? c0.n : (stage == 2 ? c1.n : c2.n);
+      const long long n_in = (stage <= 1 ? c0.n : (stage == 2 ? c1.n : c2.n)) - I->seq_base;
       ax_bits = spread_reduce_tagged(spx, 3 * n_in + slot_in);
       ay_bits = spread_reduce_tagged(spy, 3 * n_in + slot_in);
     } else {
@@ -102,7 +102,7 @@ __global__ __launch_bounds__(256) void stage2d_kernel(StageArgs a) {
   const double dt_fixed = I->dt_fixed, cfl = I->cfl, dxd = I->dx, dyd = I->dy;
   auto zero_slot = [&](int slot) {
     if (sp) {
-      if (!kTag && first_block && tid < 64) {
+      if (!kTag && first_block && tid < kSpread) {
         sp[((slot * 2 + 0) * kSpread + tid) * kSpreadStride] = 0ull;
         sp[((slot * 2 + 1) * kSpread + tid) * kSpreadStride] = 0ull;
       }
@@ -403,8 +403,8 @@ __global__ __launch_bounds__(256) void stage2d_kernel(StageArgs a) {
     } else {
       const int k = (blockIdx.y * gridDim.x + blockIdx.x) % kSpread;
       if (sp && kTag) {
-        atomicMax(&sp[((slot * 2 + 0) * kSpread + k) * kSpreadStride], spread_tag(3 * n + stage, float(bits_to_double(mx))));
-        atomicMax(&sp[((slot * 2 + 1) * kSpread + k) * kSpreadStride], spread_tag(3 * n + stage, float(bits_to_double(my))));
+        atomicMax(&sp[((slot * 2 + 0) * kSpread + k) * kSpreadStride], spread_tag(3 * (n - I->seq_base) + stage, float(bits_to_double(mx))));
+        atomicMax(&sp[((slot * 2 + 1) * kSpread + k) * kSpreadStride], spread_tag(3 * (n - I->seq_base) + stage, float(bits_to_double(my))));
       } else {
         atomicMax(sp ? &sp[((slot * 2 + 0) * kSpread + k) * kSpreadStride] : &I->alpha[slot][0], mx);
         atomicMax(sp ? &sp[((slot * 2 + 1) * kSpread + k) * kSpreadStride] : &I->alpha[slot][1], my);

@@ -55,6 +55,7 @@ struct npw_solver {
   std::vector<Tile> tiles_all;     // every tile of every instance
   std::vector<Tile> tiles_live;    // host source of the last tile-table upload (kept until the next)
   std::vector<char> settled;       // per instance: error already handled
+  long long seq_limit = 1LL << 30; // steps after seq_base at which the spread tags are rebased
 };
 
 constexpr long long kMaxNy2D = 4LL * 65535;  // tallest 2D grid (126 x 4 tiles, 65535 rows of them)
@@ -227,6 +228,23 @@ int settle_error(npw_solver* s, int b) {
 void clear_graphs(npw_solver* s) {
   for (auto& kv : s->graphs) (void)hipGraphExecDestroy(kv.second);
   s->graphs.clear();
+}
+
+// Float-bulk single grids tag their spread alpha entries with 32 bits of 3 (n - seq_base) + stage.
+// Before a graph could take that past 3 * seq_limit (2^30 steps by default, far below 2^32 / 3),
+// move seq_base to the current step and run the state check, which clears every entry and seeds
+// slot 0 with alpha of u^n under sequence 0.  NPW_SEQ_REBASE lowers the limit (for tests).
+bool tagged_spread(const npw_solver* s) { return s->spread != nullptr && s->precision == NPW_FP32; }
+
+int maybe_rebase(npw_solver* s, int k) {
+  if (!tagged_spread(s)) return NPW_OK;
+  const long long n = s->h_pin[0].ctl[0].n;
+  if (n + k - s->h_inst[0].seq_base <= s->seq_limit) return NPW_OK;
+  s->h_inst[0].seq_base = n;
+  int rc = push_static(s);
+  if (rc) return rc;
+  HIP_TRY(launch_init(s, s->stream));
+  return pull(s);
 }
 
 // Tile table of the instances flagged in `want`.  Tiles of finished instances cost one
@@ -523,6 +541,7 @@ int reset_instances(npw_solver* s, double t) {
     std::memset(h.ctl, 0, sizeof h.ctl);
     std::memset(h.alpha, 0, sizeof h.alpha);
     h.ctl[0].t = t;
+    h.seq_base = 0;
     h.err = 0;
     h.err_stage = 0;
     h.err_n = 0;
@@ -617,6 +636,10 @@ static int create_common(const npw_params* p, int32_t count, const void* const* 
   s->ninst = count;
   s->batch = batch;
   s->block = env_block();
+  if (const char* e = std::getenv("NPW_SEQ_REBASE")) {
+    const long long v = std::atoll(e);
+    if (v >= 1 && v <= (1LL << 30)) s->seq_limit = v;
+  }
   s->user = reinterpret_cast<hipStream_t>(hip_stream);
   long long off = 0;
   for (int b = 0; b < count; ++b) {
@@ -816,6 +839,8 @@ static int run_steps(npw_solver* s, const double* T, int64_t max_steps, int64_t*
     if (max_steps >= 0) want = (int)std::min<int64_t>(want, max_steps - progress);
     int k = 1;
     while (k * 4 <= want) k *= 4;
+    rc = maybe_rebase(s, k);
+    if (rc) return rc;
     hipGraphExec_t g = graph_for(s, k, home);
     if (!g) return NPW_EHIP;
     HIP_TRY(hipGraphLaunch(g, s->stream));

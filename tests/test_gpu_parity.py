@@ -148,6 +148,34 @@ def test_long_solve_across_graph_sizes_fp64():
     assert np.array_equal(u, uo)
 
 
+@pytest.mark.parametrize("dim", [1, 2])
+def test_spread_tag_rebase_changes_nothing_fp32(dim, monkeypatch):
+    """Float single grids tag their alpha entries with the stage sequence counted from a base
+    that the host moves forward (re-running the state check) long before 32 bits run out.
+    NPW_SEQ_REBASE=5 forces a rebase before almost every graph; the solve must not change."""
+    _say(f"spread tag rebase fp32 dim={dim}")
+    if dim == 1:
+        w = I.burgers_noisy(n=3000, seed=2)
+        steps = 150
+    else:
+        base = I.euler2d_quadrants(n=70, seed=5)
+        w = base.with_(ny=53, u0=base.u0.reshape(4, 70, 70)[:, :53, :].reshape(-1))
+        steps = 40
+    u32 = np.asarray(w.u0, np.float32)
+    runs = []
+    for limit in (None, "5"):
+        if limit is None:
+            monkeypatch.delenv("NPW_SEQ_REBASE", raising=False)
+        else:
+            monkeypatch.setenv("NPW_SEQ_REBASE", limit)
+        with B.Solver(u32, **B.workload_params(w, B.FP32)) as s:
+            st = s.solve(w.T, max_steps=steps)
+            runs.append((s.read(), st))
+    (u_a, st_a), (u_b, st_b) = runs
+    assert st_a["nsteps"] == st_b["nsteps"] == steps and st_a["t"] == st_b["t"]
+    assert np.array_equal(u_a, u_b)
+
+
 def test_sod_fp64():
     _say("sod N600 fp64")
     w = I.sod(600, T=0.2, cfl=0.5)
