@@ -95,6 +95,25 @@ def counter_traffic(kernel: str):
     return None
 
 
+def counter_valu(kernel: str):
+    """VALU issue utilisation of `kernel` (SQ_INSTS_VALU over 256 CUs x 2.4 GHz x duration) from the
+    VALU counter summaries under profiles/, or None when none covers this kernel as now built."""
+    key = "kernel=" + kernel.replace(" ", "")
+    src = "source=" + kernel_source_hash()
+    pdir = os.path.join(ROOT, "profiles")
+    if not os.path.isdir(pdir):
+        return None
+    for name in sorted(os.listdir(pdir)):
+        if not name.endswith("_valu_counters.txt"):
+            continue
+        with open(os.path.join(pdir, name)) as f:
+            for line in f:
+                parts = line.split()
+                if parts and parts[0] == "valu" and key in parts and src in parts:
+                    return float(next(p for p in parts if p.startswith("utilisation="))[len("utilisation="):])
+    return None
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -193,6 +212,7 @@ def bench_single(args, w, prec):
         "rk_steps_per_solve": rk,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": counter_traffic(label),
+                     "valu_issue_utilisation": counter_valu(label),
                      "kernel": label, "avg_launch_us": avg_launch * 1e6,
                      "bytes_per_launch": bytes_per_launch},
         "launch_shape": shape,
@@ -333,6 +353,7 @@ def bench_batch(args, prec):
             "max_rk_steps": max_steps,
             "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                          "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                         "valu_issue_utilisation": counter_valu(kernel_label(ws[0], prec, shape, batched=True)),
                          "kernel": kernel_label(ws[0], prec, shape, batched=True),
                          "note": "bytes of all instances / GPU time of the timed region"}}
 

@@ -56,3 +56,17 @@ def test_batch_cpu_baseline_threads_and_error(monkeypatch):
     assert base["kind"] == "oracle" and base["cores"] >= 1 and base["value"] > 0
     assert err["instances"] == len(ws)
     assert err["l1"] == 0.0 and err["linf"] == 0.0
+
+
+def test_counter_valu_requires_matching_kernel_and_source(tmp_path, monkeypatch):
+    import bench
+    h = bench.kernel_source_hash()
+    pdir = tmp_path / "profiles"
+    pdir.mkdir()
+    (pdir / "k_valu_counters.txt").write_text(
+        f"# header\nvalu kernel=stage2d_kernel<float,Euler,4,64,8,recompute> source={h} utilisation=0.896 "
+        f"wave_instr_per_cell_stage=26.1\n")
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    monkeypatch.setattr(bench, "kernel_source_hash", lambda: h)
+    assert bench.counter_valu("stage2d_kernel<float, Euler, 4, 64, 8, recompute>") == pytest.approx(0.896)
+    assert bench.counter_valu("stage2d_kernel<float, Euler, 4, 62, 8, recompute>") is None
