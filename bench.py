@@ -63,7 +63,8 @@ def kernel_label(w, prec, shape, batched=False):
 
 def scheme_of(w):
     name = {v: k for k, v in RECONS.items()}[w.recon]
-    return name + (", characteristic" if w.variables == 1 else "") + (", switch off" if w.switch_mode == 1 else "")
+    return (name + (", characteristic" if w.variables == 1 else "")
+            + (", monotone switch off" if w.switch_mode == 1 else ", monotone switch"))
 
 
 def kernel_source_hash() -> str:
