@@ -700,6 +700,15 @@ __device__ __forceinline__ R wave_max_nonneg(R v) {
   }
 }
 
+// Workgroups go to the 8 XCDs round robin (dispatch index b to XCD b % 8).  Map dispatch index b
+// of G to a tile so that each XCD owns a contiguous run of tiles (a bijection on [0, G)):
+// neighbouring tiles read each other's edge cells, and within a run they share one L2.
+__device__ __forceinline__ long long xcd_contiguous_tile(long long b, long long G) {
+  constexpr int kXcd = 8;
+  const long long q = G / kXcd, r = G % kXcd, x = b % kXcd;
+  return x * q + (x < r ? x : r) + b / kXcd;
+}
+
 // Float-bulk single grids tag every spread alpha entry with the stage that wrote it:
 // entry = (stage sequence << 32) | float bits of alpha, the sequence of RK stage k of step n being
 // 3 (n - seq_base) + k and that of the state check of u^n being 3 (n - seq_base).  Newer tags win

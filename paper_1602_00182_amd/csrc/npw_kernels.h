@@ -328,13 +328,17 @@ __global__ __launch_bounds__(BS) void stage1d_kernel(StageArgs a) {
     Tile t;
     t.inst = 0;
     t.bc = a.bc;
-    t.start = (long long)blockIdx.x * (BS - 2);
+    t.start = xcd_contiguous_tile(blockIdx.x, gridDim.x) * (BS - 2);
     t.nx = a.nx;
     t.off = 0;
     stage1d_tile<R, FLUX, M, BS, CHAR, K2>(a, t);
     return;
   }
   const int nt = a.ntiles_dev ? *a.ntiles_dev : a.ntiles;
+  if ((int)gridDim.x == nt) {  // one tile per workgroup (a batch): XCD-contiguous runs of the table
+    stage1d_tile<R, FLUX, M, BS, CHAR, K2>(a, a.tiles[xcd_contiguous_tile(blockIdx.x, nt)]);
+    return;
+  }
   for (int ti = blockIdx.x; ti < nt; ti += gridDim.x) {
     stage1d_tile<R, FLUX, M, BS, CHAR, K2>(a, a.tiles[ti]);
     __syncthreads();  // LDS is reused by the next tile

@@ -36,7 +36,19 @@ __global__ __launch_bounds__(256) void stage2d_kernel(StageArgs a) {
   const int tid = threadIdx.x;
   const int stage = a.stage;
   const int nx = (int)a.nx, ny = (int)a.ny;
-  const int i0 = blockIdx.x * TX, j0 = blockIdx.y * TY;
+  // this workgroup's tile: XCD-contiguous runs of the row-major tile order
+  const long long tile = xcd_contiguous_tile((long long)blockIdx.y * gridDim.x + blockIdx.x,
+                                             (long long)gridDim.x * gridDim.y);
+  const unsigned gx = gridDim.x;
+  int tbx, tby;
+  if (tile < (1LL << 32)) {  // 32-bit division whenever the grid allows it
+    tby = (int)((unsigned)tile / gx);
+    tbx = (int)((unsigned)tile - (unsigned)tby * gx);
+  } else {
+    tby = (int)(tile / gx);
+    tbx = (int)(tile - (long long)tby * gx);
+  }
+  const int i0 = tbx * TX, j0 = tby * TY;
   const int bc = a.bc;
   const int par = a.par;
   const long long ncell = (long long)nx * ny;
@@ -73,10 +85,10 @@ __global__ __launch_bounds__(256) void stage2d_kernel(StageArgs a) {
     }
   }
 
-  // ---- step control (same protocol as the 1D kernel; the lead is block (0, 0)) -------------
+  // ---- step control (same protocol as the 1D kernel; the lead is tile (0, 0)) --------------
   InstDev* I = a.inst;
   unsigned long long* sp = a.spread;
-  const bool first_block = (blockIdx.x == 0 && blockIdx.y == 0);
+  const bool first_block = (tbx == 0 && tby == 0);
   const bool lead = first_block && tid == 0;
   constexpr bool kTag = !kExact;  // float bulk: spread entries carry their stage sequence
   const int slot_in = stage == 0 ? 0 : stage - 1;
