@@ -65,7 +65,9 @@ namespace {
 
 // Steps per captured graph (3 stage kernels each).  The host reads the instance table back after
 // every graph, which leaves the device idle for ~40 us; a single grid amortises that over 1024
-// steps, while a batch keeps 256 so that its tile table drops finished instances sooner.
+// steps once at least 8 such graphs remain (instantiating a 3072-node graph costs milliseconds,
+// which a short solve would not earn back), while a batch keeps 256 so that its tile table drops
+// finished instances sooner.
 constexpr int kMaxGraphStepsSingle = 1024;
 constexpr int kMaxGraphStepsBatch = 256;
 
@@ -835,7 +837,8 @@ static int run_steps(npw_solver* s, const double* T, int64_t max_steps, int64_t*
       rc = set_tiles(s, active, launched == 0);
       if (rc) return rc;
     }
-    int want = est < 1.0 ? 1 : (int)std::min((double)max_k, std::ceil(est));
+    const int cap = (max_k > kMaxGraphStepsBatch && est < 8.0 * max_k) ? kMaxGraphStepsBatch : max_k;
+    int want = est < 1.0 ? 1 : (int)std::min((double)cap, std::ceil(est));
     if (max_steps >= 0) want = (int)std::min<int64_t>(want, max_steps - progress);
     int k = 1;
     while (k * 4 <= want) k *= 4;

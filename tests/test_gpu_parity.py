@@ -148,6 +148,23 @@ def test_long_solve_across_graph_sizes_fp64():
     assert np.array_equal(u, uo)
 
 
+def test_long_fixed_dt_solve_through_1024_step_graphs_fp64():
+    """10000 fixed steps (binary dt, so t sums exactly): the solve replays 1024-step graphs while
+    at least 8 of them remain, then 256, 64, 16, 4 and 1; interrupted at 9000 and resumed, it
+    must still follow the oracle bit for bit."""
+    _say("advection N256 10000 fixed steps fp64")
+    d = 2.0 ** -12
+    w = I.advection_sine(256, T=10000 * d, dt_fixed=d)
+    with _solver(w) as s:
+        st1 = s.solve(w.T, max_steps=9000)
+        assert st1["nsteps"] == 9000
+        st = s.solve(w.T)
+        u = s.read()
+    uo, to, no = O.solve(_oracle_problem(w), w.u0, w.T)
+    assert st["nsteps"] == no == 10000 and st["t"] == to
+    assert np.array_equal(u, uo)
+
+
 @pytest.mark.parametrize("dim", [1, 2])
 def test_spread_tag_rebase_changes_nothing_fp32(dim, monkeypatch):
     """Float single grids tag their alpha entries with the stage sequence counted from a base
