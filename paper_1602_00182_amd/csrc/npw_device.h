@@ -244,15 +244,19 @@ __device__ __forceinline__ int eno_stencil(double a, double b, double c, double 
   return left;
 }
 
-// Table 3 row `row` (-1..2) chosen at run time.
+// Table 3 row `row` (-1..2) chosen at run time, without branches (neighbouring lanes of a wave
+// often pick different rows).  Rows 1 and 2 are rows 0 and -1 read backwards, so the six distinct
+// coefficients c_rj + eta p_rj are formed once and selected; each is the same expression as in
+// table3_row, and the sum runs in the same order, so the result is identical.
 template <typename R>
 __device__ __forceinline__ R table3_row_rt(int row, R w0, R w1, R w2, R eta) {
-  switch (row) {
-    case -1: return table3_row<R, -1>(w0, w1, w2, eta);
-    case 0: return table3_row<R, 0>(w0, w1, w2, eta);
-    case 1: return table3_row<R, 1>(w0, w1, w2, eta);
-    default: return table3_row<R, 2>(w0, w1, w2, eta);
-  }
+  const R k0 = R(1.0 / 3.0) + eta * R(5.0 / 6.0), k1 = R(5.0 / 6.0) + eta * R(-2.0 / 3.0),
+          k2 = R(-1.0 / 6.0) + eta * R(-1.0 / 6.0);  // row 0; row 1 is (k2, k1, k0)
+  const R m0 = R(11.0 / 6.0) + eta * R(-9.0 / 2.0), m1 = R(-7.0 / 6.0) + eta * R(6.0),
+          m2 = R(1.0 / 3.0) + eta * R(-3.0 / 2.0);  // row -1; row 2 is (m2, m1, m0)
+  const bool outer = row < 0 || row > 1, flip = row > 0;
+  const R a = outer ? m0 : k0, b = outer ? m1 : k1, c = outer ? m2 : k2;
+  return (flip ? c : a) * w0 + b * w1 + (flip ? a : c) * w2;
 }
 
 // ENO edge values of a cell with stencil r, window (a..e): v^- uses row r, v^+ row r-1.
