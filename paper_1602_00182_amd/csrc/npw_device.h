@@ -259,16 +259,25 @@ __device__ __forceinline__ R table3_row_rt(int row, R w0, R w1, R w2, R eta) {
   return (flip ? c : a) * w0 + b * w1 + (flip ? a : c) * w2;
 }
 
-// ENO edge values of a cell with stencil r, window (a..e): v^- uses row r, v^+ row r-1.
+// ENO edge values of a cell with stencil r, window (a..e): v^- uses row r, v^+ row r-1, both on
+// the cells (u_{i-r}, u_{i-r+1}, u_{i-r+2}), selected without branches.
+template <typename R>
+__device__ __forceinline__ void eno_cells(int r, R a, R b, R c, R d, R e, R& w0, R& w1, R& w2) {
+  w0 = r == 0 ? c : (r == 1 ? b : a);
+  w1 = r == 0 ? d : (r == 1 ? c : b);
+  w2 = r == 0 ? e : (r == 1 ? d : c);
+}
 template <typename R>
 __device__ __forceinline__ R eno_minus(int r, R a, R b, R c, R d, R e, R eta) {
-  const R w[5] = {a, b, c, d, e};
-  return table3_row_rt<R>(r, w[2 - r], w[3 - r], w[4 - r], eta);
+  R w0, w1, w2;
+  eno_cells<R>(r, a, b, c, d, e, w0, w1, w2);
+  return table3_row_rt<R>(r, w0, w1, w2, eta);
 }
 template <typename R>
 __device__ __forceinline__ R eno_plus(int r, R a, R b, R c, R d, R e, R eta) {
-  const R w[5] = {a, b, c, d, e};
-  return table3_row_rt<R>(r - 1, w[2 - r], w[3 - r], w[4 - r], eta);
+  R w0, w1, w2;
+  eno_cells<R>(r, a, b, c, d, e, w0, w1, w2);
+  return table3_row_rt<R>(r - 1, w0, w1, w2, eta);
 }
 
 template <typename R>
