@@ -90,7 +90,9 @@ hipError_t launch_stage_f32(int flux, int ncomp, int block, const StageArgs& a, 
 // 2D launch shapes: tiles 0 = 64 x 8, 1 = 62 x 8, 2 = 126 x 4 cells with per-cell values shared
 // through LDS; 3, 4, 5 = the same tiles with those values recomputed per interface.  (Taller
 // recomputed tiles, 64 x 12 and 64 x 16, do less halo work along y but hold more LDS; measured
-// slower on 2048^2 Euler: 211 and 251 us per stage against 193 us for 64 x 8.)
+// slower on 2048^2 Euler: 211 and 251 us per stage against 193 us for 64 x 8.  Recomputed 63 x 8,
+// whose x sweep fills exactly 8 waves, measured the same as 64 x 8 (187.8-188.6 us); 127 x 4 took
+// 250 us.)
 constexpr int k2dShapes = 6;
 hipError_t launch_stage2d_f64(int flux, int ncomp, int shape, const StageArgs& a, hipStream_t s);
 hipError_t launch_stage2d_f32(int flux, int ncomp, int shape, const StageArgs& a, hipStream_t s);

@@ -39,14 +39,14 @@ __global__ __launch_bounds__(256) void stage2d_kernel(StageArgs a) {
   // this workgroup's tile: XCD-contiguous runs of the row-major tile order
   const long long tile = xcd_contiguous_tile((long long)blockIdx.y * gridDim.x + blockIdx.x,
                                              (long long)gridDim.x * gridDim.y);
-  const unsigned gx = gridDim.x;
+  const unsigned grid_x = gridDim.x;
   int tbx, tby;
   if (tile < (1LL << 32)) {  // 32-bit division whenever the grid allows it
-    tby = (int)((unsigned)tile / gx);
-    tbx = (int)((unsigned)tile - (unsigned)tby * gx);
+    tby = (int)((unsigned)tile / grid_x);
+    tbx = (int)((unsigned)tile - (unsigned)tby * grid_x);
   } else {
-    tby = (int)(tile / gx);
-    tbx = (int)(tile - (long long)tby * gx);
+    tby = (int)(tile / grid_x);
+    tbx = (int)(tile - (long long)tby * grid_x);
   }
   const int i0 = tbx * TX, j0 = tby * TY;
   const int bc = a.bc;
