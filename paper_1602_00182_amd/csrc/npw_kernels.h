@@ -271,15 +271,10 @@ __device__ __forceinline__ void stage1d_tile(const StageArgs& a, const Tile tile
         L = -div_rn(s_F[c][tid] - s_F[c][tid - 1], dx);
       else
         L = (s_F[c][tid - 1] - s_F[c][tid]) * inv_dx;
-      if (stage == 0) {
+      if (stage == 0)
         unew[c] = L;
-      } else if (stage == 1) {
-        unew[c] = s_u[c][tid + 2] + rdt * L;
-      } else if (stage == 2) {
-        unew[c] = R(0.75) * upt[c] + R(0.25) * (s_u[c][tid + 2] + rdt * L);
-      } else {
-        unew[c] = R(1.0 / 3.0) * upt[c] + R(2.0 / 3.0) * (s_u[c][tid + 2] + rdt * L);
-      }
+      else
+        unew[c] = rk3_combine<R>(stage, upt[c], s_u[c][tid + 2], rdt * L);
       dst[c * nx + cell] = unew[c];
     }
     if (stage != 0) amax = spectral_radius<R, FLUX, M, 0>(unew, speed, gamma, bad);

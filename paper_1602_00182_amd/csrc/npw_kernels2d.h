@@ -366,12 +366,8 @@ __global__ __launch_bounds__(256) void stage2d_kernel(StageArgs a) {
       const R us = s_u[c][y + 3][x + 3];
       if (stage == 0)
         unew[c] = L;
-      else if (stage == 1)
-        unew[c] = us + rdt * L;
-      else if (stage == 2)
-        unew[c] = R(0.75) * upt[k][c] + R(0.25) * (us + rdt * L);
       else
-        unew[c] = R(1.0 / 3.0) * upt[k][c] + R(2.0 / 3.0) * (us + rdt * L);
+        unew[c] = rk3_combine<R>(stage, upt[k][c], us, rdt * L);
       dst[c * ncell + at] = unew[c];
     }
     if (stage != 0) {

@@ -268,6 +268,22 @@ def test_rhs_fp32_one_stage():
     assert np.max(np.abs(L - Lo)) <= tol
 
 
+def test_fp32_error_does_not_drift_over_long_runs():
+    """The float bulk's RK3 combination carries no per-step bias: on smooth advection, 3000 steps
+    stay within 2e-6 of the FP64 oracle in L1.  With 1/3 and 2/3 rounded to float in the written
+    form, the state would grow by 3e-8 per step, and L1 would reach about 4e-5 here."""
+    _say("fp32 drift advection N2048 3000 steps")
+    w = I.advection_sine(2048, T=100.0)
+    u32 = np.asarray(w.u0, np.float32)
+    with _solver(w, B.FP32, u32) as s:
+        s.solve(w.T, max_steps=3000)
+        u = s.read().astype(np.float64)
+    uo, _, no = O.solve(_oracle_problem(w), u32.astype(np.float64), w.T, max_steps=3000)
+    assert no == 3000
+    assert np.mean(np.abs(u - uo)) <= 2e-6
+    assert np.max(np.abs(u - uo)) <= 2e-5
+
+
 def test_sod_fp32():
     _say("sod fp32")
     w = I.sod(600, T=0.2)
