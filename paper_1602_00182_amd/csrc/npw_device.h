@@ -26,36 +26,38 @@ __device__ __forceinline__ int ghost_index(int k, int n, int bc) {
   return k < 0 ? 0 : n - 1;
 }
 
-// Correctly rounded double division (round to nearest, ties to even).  The instruction
-// sequence behind the '/' operator keeps the quotient within one unit in the last place but can
-// return the neighbour of the nearest double (observed on operands of the scheme).  The residual
-// a - q b is exact for a faithful q (one fused multiply-add), so comparing it with the residual
-// of the neighbour on the side of the exact quotient picks the nearest double.  Zero, subnormal,
-// huge and non-finite operands or quotients keep the hardware result.
-__device__ __forceinline__ double div_rn(double a, double b) {
-  const double q = a / b;
-  const double aq = fabs(q), aa = fabs(a), ab = fabs(b);
-  if (!(aq > 0x1p-900 && aq < 0x1p900 && aa > 0x1p-900 && aa < 0x1p900 && ab > 0x1p-900 && ab < 0x1p900)) return q;
-  const double r = fma(-q, b, a);
-  if (r == 0.0) return q;
-  const bool up = (r > 0.0) == (b > 0.0);  // the exact quotient lies above q
-  const long long bits = __double_as_longlong(q);
-  const long long nb = ((q > 0.0) == up) ? bits + 1 : bits - 1;
-  const double q1 = __longlong_as_double(nb);
-  const double e0 = fabs(r), e1 = fabs(fma(-q1, b, a));
-  if (e1 < e0 || (e1 == e0 && (nb & 1) == 0)) return q1;
-  return q;
-}
 // Faithful double quotient (error below one unit in the last place) for normal operands: the
 // hardware reciprocal, one Newton step (relative error about the square of the reciprocal's) and
 // one residual correction.  (Checked against the correctly rounded quotient on 4 million operand
 // pairs spanning 1e-12..1e6: all equal.)  Used by the float bulk path for double ratios that are
-// rounded to float afterwards.
+// rounded to float afterwards, and as the first step of div_rn.
 __device__ __forceinline__ double div_faithful(double a, double b) {
   double r = __builtin_amdgcn_rcp(b);
   r = fma(fma(-b, r, 1.0), r, r);
   const double q = a * r;
   return fma(fma(-b, q, a), r, q);
+}
+
+// Correctly rounded double division (round to nearest, ties to even).  The instruction sequence
+// behind the '/' operator keeps the quotient within one unit in the last place but can return the
+// neighbour of the nearest double (observed on operands of the scheme).  Here a faithful quotient
+// q comes from div_faithful; the residual a - q b of a faithful q is exact (one fused
+// multiply-add), and so is that of its neighbour q1 on the side of the exact quotient, so the
+// smaller residual picks the nearest double.  Both candidates are formed without branches, so the
+// independent divisions of a reconstruction overlap.  Operands or quotients outside
+// [2^-900, 2^900] in magnitude (zero, subnormal, huge, non-finite) take the '/' sequence.
+__device__ __forceinline__ double div_rn(double a, double b) {
+  const double q = div_faithful(a, b);
+  const double aq = fabs(q), aa = fabs(a), ab = fabs(b);
+  if (!(aq > 0x1p-900 && aq < 0x1p900 && aa > 0x1p-900 && aa < 0x1p900 && ab > 0x1p-900 && ab < 0x1p900))
+    return a / b;
+  const double r = fma(-q, b, a);
+  const bool up = (r > 0.0) == (b > 0.0);  // the exact quotient lies above q
+  const long long bits = __double_as_longlong(q);
+  const long long nb = ((q > 0.0) == up) ? bits + 1 : bits - 1;
+  const double q1 = __longlong_as_double(nb);
+  const double e0 = fabs(r), e1 = fabs(fma(-q1, b, a));
+  return (e1 < e0 || (e1 == e0 && (nb & 1) == 0)) ? q1 : q;
 }
 
 // Division and square root in the bulk precision: correctly rounded in double (the exact
