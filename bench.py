@@ -119,8 +119,8 @@ def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None,
-                    help="timed whole solves (default: 20 for burgers, so p50/p99 rest on 20 samples; 2 for "
-                         "euler_batch; 1 for euler2d, whose solve takes ~15 s)")
+                    help="timed whole solves (default: 20 for burgers and advection, so p50/p99 rest on 20 "
+                         "samples; 3 for advection2d; 2 for euler_batch; 1 for euler2d, whose solve takes ~9 s)")
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", choices=["burgers", "advection", "euler2d", "advection2d", "euler_batch", "serving"],
                     default="burgers")
