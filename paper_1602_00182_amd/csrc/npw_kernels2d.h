@@ -28,7 +28,6 @@ __global__ __launch_bounds__(256) void stage2d_kernel(StageArgs a) {
   __shared__ unsigned char s_flag[M][NC];
   __shared__ R s_den[SHARE ? M : 1][3][SHARE ? NC : 1];
   __shared__ R s_F[M][NC];
-  __shared__ R s_L[M][TY][TX];
   static_assert(TX % 1 == 0 && TY % 1 == 0 && NC >= (TX + 2) * TY, "sweep buffers");
   __shared__ unsigned long long s_red[2][BS / 64];
   __shared__ int s_bad[BS / 64];
@@ -188,6 +187,11 @@ __global__ __launch_bounds__(256) void stage2d_kernel(StageArgs a) {
   }
   __syncthreads();
 
+  R Lr[NOWN][M];  // L(u) of this thread's owned cells (x sweep, then + y sweep)
+#pragma unroll
+  for (int k = 0; k < NOWN; ++k)
+#pragma unroll
+    for (int c = 0; c < M; ++c) Lr[k][c] = R(0);
   // One sweep direction.  Cells along the sweep are addressed by (line, pos): pos runs over
   // -1..LEN (LEN = TX for x, TY for y), line over the other tile extent; q = pos + 3 is the
   // staged coordinate along the sweep.  Work items are numbered so that consecutive threads
@@ -324,8 +328,12 @@ __global__ __launch_bounds__(256) void stage2d_kernel(StageArgs a) {
       for (int c = 0; c < M; ++c) s_F[c][wl] = H[c];
     }
     __syncthreads();
-    // flux difference into the owned cells
-    for (int o = tid; o < TX * TY; o += BS) {
+    // flux difference into the owned cells; thread tid owns cells tid + k BS in both sweeps and in
+    // the update, so L stays in its registers
+#pragma unroll
+    for (int k = 0; k < NOWN; ++k) {
+      const int o = tid + k * BS;
+      if (o >= TX * TY) continue;
       const int x = o % TX, y = o / TX;
       const int line = DIR == 0 ? y : x, pos = DIR == 0 ? x : y;
       const int wp = cid(line, pos), wm = cid(line, pos - 1);  // interfaces pos+1/2 and pos-1/2
@@ -334,14 +342,14 @@ __global__ __launch_bounds__(256) void stage2d_kernel(StageArgs a) {
         const R Fp = s_F[c][wp], Fm = s_F[c][wm];
         if constexpr (DIR == 0) {
           if constexpr (kExact)
-            s_L[c][y][x] = -div_rn(Fp - Fm, dx);
+            Lr[k][c] = -div_rn(Fp - Fm, dx);
           else
-            s_L[c][y][x] = (Fm - Fp) * inv_dx;
+            Lr[k][c] = (Fm - Fp) * inv_dx;
         } else {
           if constexpr (kExact)
-            s_L[c][y][x] = s_L[c][y][x] - div_rn(Fp - Fm, dy);
+            Lr[k][c] = Lr[k][c] - div_rn(Fp - Fm, dy);
           else
-            s_L[c][y][x] = s_L[c][y][x] + (Fm - Fp) * inv_dy;
+            Lr[k][c] = Lr[k][c] + (Fm - Fp) * inv_dy;
         }
       }
     }
@@ -362,7 +370,7 @@ __global__ __launch_bounds__(256) void stage2d_kernel(StageArgs a) {
     R unew[M];
 #pragma unroll
     for (int c = 0; c < M; ++c) {
-      const R L = s_L[c][y][x];
+      const R L = Lr[k][c];
       const R us = s_u[c][y + 3][x + 3];
       if (stage == 0)
         unew[c] = L;
