@@ -25,9 +25,12 @@ __global__ __launch_bounds__(256) void stage2d_kernel(StageArgs a) {
   constexpr int WX = TX + 6, WY = TY + 6;                          // staged cells per row / column
   constexpr int NC = (TX + 2) * TY > TX * (TY + 2) ? (TX + 2) * TY : TX * (TY + 2);  // sweep cells
   __shared__ R s_u[M][WY][WX];
-  __shared__ unsigned char s_flag[M][NC];
+  // interface fluxes are stored at the left cell's index, which stays below NF in both sweeps
+  constexpr int NF = (TX + 2) * TY > (TY + 1) * TX ? (TX + 2) * TY : (TY + 1) * TX;
+  // per-cell flags (bit 0 switch, bits 1-2 ENO stencil) of two components share a byte
+  __shared__ unsigned char s_flag[(M + 1) / 2][NC];
   __shared__ R s_den[SHARE ? M : 1][3][SHARE ? NC : 1];
-  __shared__ R s_F[M][NC];
+  __shared__ R s_F[M][NF];
   static_assert(TX % 1 == 0 && TY % 1 == 0 && NC >= (TX + 2) * TY, "sweep buffers");
   __shared__ unsigned long long s_red[2][BS / 64];
   __shared__ int s_bad[BS / 64];
@@ -192,6 +195,7 @@ __global__ __launch_bounds__(256) void stage2d_kernel(StageArgs a) {
   for (int k = 0; k < NOWN; ++k)
 #pragma unroll
     for (int c = 0; c < M; ++c) Lr[k][c] = R(0);
+  auto FL = [&](int c, int w) -> int { return (s_flag[c / 2][w] >> (4 * (c % 2))) & 15; };
   // One sweep direction.  Cells along the sweep are addressed by (line, pos): pos runs over
   // -1..LEN (LEN = TX for x, TY for y), line over the other tile extent; q = pos + 3 is the
   // staged coordinate along the sweep.  Work items are numbered so that consecutive threads
@@ -240,7 +244,10 @@ __global__ __launch_bounds__(256) void stage2d_kernel(StageArgs a) {
           s_den[c][1][w] = d1;
           s_den[c][2][w] = d2;
         }
-        s_flag[c][w] = (unsigned char)fl;
+        if (c % 2 == 0)
+          s_flag[c / 2][w] = (unsigned char)fl;
+        else
+          s_flag[c / 2][w] = (unsigned char)(s_flag[c / 2][w] | (fl << 4));
       }
     }
     __syncthreads();
@@ -275,18 +282,18 @@ __global__ __launch_bounds__(256) void stage2d_kernel(StageArgs a) {
             er = s_den[c][1][wr];
           } else {  // right-edge parameter of the left cell, left-edge parameter of the right cell
             double dl = 0.0, dr = 0.0;
-            if (use_eta && !(s_flag[c][wl] & 1))
+            if (use_eta && !(FL(c, wl) & 1))
               dl = eta2_ratio<kExact>(double(U(c, line, q - 1)), double(U(c, line, q)), double(U(c, line, q + 1)),
                                       eps_m);
-            if (use_eta && !(s_flag[c][wr] & 1))
+            if (use_eta && !(FL(c, wr) & 1))
               dr = eta2_ratio<kExact>(double(U(c, line, q + 2)), double(U(c, line, q + 1)), double(U(c, line, q)),
                                       eps_m);
             el = R(dl);
             er = R(dr);
           }
           if (eno) {
-            A[c] = eno2<R, false>((s_flag[c][wl] >> 1) & 1, U(c, line, q - 1), U(c, line, q), U(c, line, q + 1), el);
-            B[c] = eno2<R, true>((s_flag[c][wr] >> 1) & 1, U(c, line, q), U(c, line, q + 1), U(c, line, q + 2), er);
+            A[c] = eno2<R, false>((FL(c, wl) >> 1) & 1, U(c, line, q - 1), U(c, line, q), U(c, line, q + 1), el);
+            B[c] = eno2<R, true>((FL(c, wr) >> 1) & 1, U(c, line, q), U(c, line, q + 1), U(c, line, q + 2), er);
           } else {
             A[c] = weno3<R, false>(U(c, line, q - 1), U(c, line, q), U(c, line, q + 1), el, eps);
             B[c] = weno3<R, true>(U(c, line, q), U(c, line, q + 1), U(c, line, q + 2), er, eps);
@@ -297,13 +304,13 @@ __global__ __launch_bounds__(256) void stage2d_kernel(StageArgs a) {
         if (use_eta) {
           e = eta_ratio<kExact>(double(U(c, line, q - 1)), double(U(c, line, q)), double(U(c, line, q + 1)),
                         double(U(c, line, q + 2)), eps_m);
-          if (use_switch && ((s_flag[c][wl] | s_flag[c][wr]) & 1)) e = 0.0;
+          if (use_switch && ((FL(c, wl) | FL(c, wr)) & 1)) e = 0.0;
         }
         const R eta = R(e);
         if (eno) {
-          A[c] = eno_minus<R>(s_flag[c][wl] >> 1, U(c, line, q - 2), U(c, line, q - 1), U(c, line, q),
+          A[c] = eno_minus<R>(FL(c, wl) >> 1, U(c, line, q - 2), U(c, line, q - 1), U(c, line, q),
                               U(c, line, q + 1), U(c, line, q + 2), eta);
-          B[c] = eno_plus<R>(s_flag[c][wr] >> 1, U(c, line, q - 1), U(c, line, q), U(c, line, q + 1),
+          B[c] = eno_plus<R>(FL(c, wr) >> 1, U(c, line, q - 1), U(c, line, q), U(c, line, q + 1),
                              U(c, line, q + 2), U(c, line, q + 3), eta);
         } else if constexpr (SHARE) {
           A[c] = weno_minus<R>(U(c, line, q - 2), U(c, line, q - 1), U(c, line, q), U(c, line, q + 1),
