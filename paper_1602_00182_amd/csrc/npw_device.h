@@ -481,11 +481,11 @@ __device__ __forceinline__ void window_states(const R* w, const double* wd, cons
 // Eigen-system of the Euler flux Jacobian along DIR at the Roe average of the states UL, UR
 // (conservative; M = 3 in 1D, 4 in 2D): Lm rows are left eigenvectors, Rm columns right
 // eigenvectors, for the waves (normal velocity - c, contact [, shear], + c).  The double flavour
-// evaluates every entry in the order written, uncontracted, so it reproduces a plain evaluation
-// of the same formulas bit for bit.
+// evaluates every entry in the order written, uncontracted (its translation unit is built without
+// FP contraction), so it reproduces a plain evaluation of the same formulas bit for bit; the float
+// flavour may fuse multiply-adds.
 template <typename R, int M, int DIR>
 __device__ __forceinline__ void char_basis(const R* UL, const R* UR, R gamma, R (&Lm)[M][M], R (&Rm)[M][M]) {
-#pragma clang fp contract(off)
   const R g1 = gamma - R(1.0);
   const R rl = UL[0], rr = UR[0];
   const R ul = fdiv(UL[1], rl), ur = fdiv(UR[1], rr);
@@ -552,7 +552,7 @@ __device__ __forceinline__ void char_basis(const R* UL, const R* UR, R gamma, R 
 template <typename R, int M, int DIR>
 __device__ __forceinline__ void char_states(const R (&U)[6][M], R gamma, const ReconMode rm, R eps, double eps_m,
                                             R* A, R* B) {
-#pragma clang fp contract(off)
+  // (double: uncontracted by its translation unit's build flags; float: projections may fuse)
   R Lm[M][M], Rm[M][M];
   char_basis<R, M, DIR>(U[2], U[3], gamma, Lm, Rm);
   R wm[M], wp[M];
