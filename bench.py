@@ -137,6 +137,9 @@ def parse():
     ap.add_argument("--variables", choices=["componentwise", "characteristic"], default="componentwise",
                     help="Euler reconstruction variables (euler_batch and euler2d)")
     ap.add_argument("--serving-requests", type=int, default=200)
+    ap.add_argument("--serving-nmax", type=int, default=16384,
+                    help="upper end of the request grid sizes: N is drawn log-uniform in [256, nmax] "
+                         "(262144 for the full trace)")
     ap.add_argument("--pump-steps", type=int, default=64, help="RK steps per serving pump (admission granularity)")
     return ap.parse_args()
 
@@ -365,7 +368,7 @@ def bench_serving(args, prec):
     from paper_1602_00182_amd import binding as B
     from paper_1602_00182_amd import inputs as I
     nreq = args.serving_requests
-    trace = I.serving_trace(nreq=nreq, seed=4, nmax=16384)
+    trace = I.serving_trace(nreq=nreq, seed=4, nmax=args.serving_nmax)
     dt = np.float32 if prec == B.FP32 else np.float64
     work = 0.0
     srv = B.Server(1 << 30, max_slots=512, precision=prec)
@@ -406,7 +409,7 @@ def bench_serving(args, prec):
     return {"value": work / wall, "requests": nreq, "wall_s": wall, "latency_s": _percentiles(lat),
             "one_at_a_time": {"value": work / wall1, "wall_s": wall1, "latency_s": _percentiles(lat1)},
             "offered_rate_req_s": 2000.0, "pump_steps": args.pump_steps,
-            "trace": f"first {nreq} requests of the seed-4 Poisson trace, N capped at 16384"}
+            "trace": f"first {nreq} requests of the seed-4 Poisson trace, N log-uniform in [256, {args.serving_nmax}]"}
 
 
 def main():
