@@ -283,18 +283,22 @@ __device__ __forceinline__ void stage1d_tile(const StageArgs& a, const Tile tile
   // ---- epilogue: alpha of the new state and validity -------------------------------------
   amax = wave_max_nonneg(amax);
   const bool bad2 = __any(bad == 2), bad1 = __any(bad == 1);
-  if ((tid & 63) == 0) {
-    s_red[tid >> 6] = double_to_bits(double(amax));
-    s_bad[tid >> 6] = bad2 ? 2 : (bad1 ? 1 : 0);
+  if constexpr (BS > 64) {  // combine the waves through LDS (a one-wave workgroup needs no barrier)
+    if ((tid & 63) == 0) {
+      s_red[tid >> 6] = double_to_bits(double(amax));
+      s_bad[tid >> 6] = bad2 ? 2 : (bad1 ? 1 : 0);
+    }
+    __syncthreads();
   }
-  __syncthreads();
   if (tid == 0) {
-    unsigned long long m = 0ull;
-    int w = 0;
+    unsigned long long m = double_to_bits(double(amax));
+    int w = bad2 ? 2 : (bad1 ? 1 : 0);
+    if constexpr (BS > 64) {
 #pragma unroll
-    for (int k = 0; k < BS / 64; ++k) {
-      m = s_red[k] > m ? s_red[k] : m;
-      w = s_bad[k] > w ? s_bad[k] : w;
+      for (int k = 1; k < BS / 64; ++k) {
+        m = s_red[k] > m ? s_red[k] : m;
+        w = s_bad[k] > w ? s_bad[k] : w;
+      }
     }
     const int slot = stage == 1 ? 1 : (stage == 2 ? 2 : 0);
     if (w) {
