@@ -21,6 +21,16 @@
 
 namespace npw {
 
+// Barrier between the phases of a tile.  A one-wave workgroup needs none: a wave's LDS accesses
+// complete in program order, so it only has to keep the compiler from moving them across.
+template <int BS>
+__device__ __forceinline__ void tile_barrier() {
+  if constexpr (BS == 64)
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  else
+    __syncthreads();
+}
+
 template <typename R, int FLUX, int M, int BS, bool CHAR, bool K2>
 __device__ __forceinline__ void stage1d_tile(const StageArgs& a, const Tile tile) {
   constexpr bool kExact = std::is_same<R, double>::value;
@@ -170,7 +180,7 @@ __device__ __forceinline__ void stage1d_tile(const StageArgs& a, const Tile tile
       if constexpr (!kExact) s_d[c][BS + tid] = double(ld1[c]);
     }
   }
-  __syncthreads();
+  tile_barrier<BS>();
   auto D = [&](int c, int idx) -> double {
     if constexpr (kExact)
       return s_u[c][idx];
@@ -209,7 +219,7 @@ __device__ __forceinline__ void stage1d_tile(const StageArgs& a, const Tile tile
     }
     s_flag[c][tid] = (unsigned char)fl;
   }
-  __syncthreads();
+  tile_barrier<BS>();
   // ---- interface phase: x_{cell+1/2} between cell start-1+tid and the next (tid < BS-1) ----
   // eta (Table 3 caption) zeroed by the switch, v^- of the left cell, v^+ of the right cell,
   // and the global Lax-Friedrichs flux.
@@ -258,7 +268,7 @@ __device__ __forceinline__ void stage1d_tile(const StageArgs& a, const Tile tile
 #pragma unroll
     for (int c = 0; c < M; ++c) s_F[c][tid] = H[c];
   }
-  __syncthreads();
+  tile_barrier<BS>();
   // ---- update of the owned cells (tid = 1 .. BS-2) ---------------------------------------------
   R amax = R(0);
   int bad = 0;
