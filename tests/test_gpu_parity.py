@@ -81,6 +81,25 @@ def test_rhs_every_block_size_fp64(block, monkeypatch):
         assert np.array_equal(u, uo)
 
 
+@pytest.mark.parametrize("block", ["64", "128", "256", "512"])
+@pytest.mark.parametrize("variables,recon", [(I.COMPONENTWISE, I.RBF_WENO5), (I.COMPONENTWISE, I.RBF_ENO3),
+                                             (I.COMPONENTWISE, I.RBF_WENO3), (I.CHARACTERISTIC, I.RBF_WENO5)])
+def test_euler_steps_every_block_size_fp64(block, variables, recon, monkeypatch):
+    """Euler (three components) through every workgroup size, including the one-wave workgroup
+    whose phases are separated by compiler fences only: bit for bit against the oracle."""
+    _say(f"euler block={block} variables={variables} recon={recon}")
+    monkeypatch.setenv("NPW_BLOCK", block)
+    w = I.euler_riemann_batch(count=1, seed=11, nmin=700, nmax=700)[0].with_(recon=recon, variables=variables)
+    with _solver(w) as s:
+        assert s.launch_shape()["block"] == int(block)
+        s.solve(w.T, max_steps=12)
+        u = s.read()
+    pb = _oracle_problem(w, charwise=1 if variables == I.CHARACTERISTIC else 0)
+    uo, _, no = O.solve(pb, w.u0, w.T, max_steps=12)
+    assert no == 12
+    assert np.array_equal(u, uo)
+
+
 @pytest.mark.parametrize("recon,sw", [(I.RBF_WENO5, I.SWITCH_MONOTONE), (I.RBF_WENO5, I.SWITCH_OFF),
                                       (I.WENO5_JS, I.SWITCH_MONOTONE), (I.RBF_ENO3, I.SWITCH_MONOTONE),
                                       (I.RBF_ENO3, I.SWITCH_OFF), (I.ENO3, I.SWITCH_MONOTONE)])
