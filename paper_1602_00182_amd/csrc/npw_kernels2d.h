@@ -27,6 +27,9 @@ __global__ __launch_bounds__(256) void stage2d_kernel(StageArgs a) {
   __shared__ R s_u[M][WY][WX];
   // interface fluxes are stored at the left cell's index, which stays below NF in both sweeps
   constexpr int NF = (TX + 2) * TY > (TY + 1) * TX ? (TX + 2) * TY : (TY + 1) * TX;
+  // one wave per row in the x sweep: cells -1..TX of a row fill a wave exactly (scalar flags and
+  // per-interface denominators only)
+  constexpr bool kRowWave = TX + 2 == 64 && !CHAR && !K2 && !SHARE;
   // per-cell flags (bit 0 switch, bits 1-2 ENO stencil) of two components share a byte
   __shared__ unsigned char s_flag[(M + 1) / 2][NC];
   __shared__ R s_den[SHARE ? M : 1][3][SHARE ? NC : 1];
@@ -208,9 +211,56 @@ __global__ __launch_bounds__(256) void stage2d_kernel(StageArgs a) {
     constexpr int NPOS = LEN + 2;  // cells -1 .. LEN
     auto U = [&](int c, int line, int q) -> R { return DIR == 0 ? s_u[c][line + 3][q] : s_u[c][q][line + 3]; };
     auto cid = [&](int line, int pos) -> int { return DIR == 0 ? line * NPOS + pos + 1 : (pos + 1) * LINES + line; };
+    // x sweep with one wave per row, for tiles whose staged row holds cells -1..TX in exactly one
+    // wave: lane l takes cell p = l - 1 and forms its flag, weight denominators, eta_{p+1/2} and
+    // both edge values once; the next cell's flag, eta_{p-1/2} and v^+_{p+1/2} arrive by lane
+    // shuffles.  Same functions on the same operands as the two phases below, so the fluxes are
+    // identical; the separate flag pass and its barrier go away, and so does the second
+    // denominator set of every interface.
+    bool rows = false;
+    if constexpr (DIR == 0 && kRowWave) {
+      rows = !cross;
+      if (rows) {
+        const int lane = tid & 63, q = lane + 2;  // q = p + 3
+        for (int line = tid >> 6; line < LINES; line += BS / 64) {
+          R A[M], B[M], H[M];
+#pragma unroll
+          for (int c = 0; c < M; ++c) {
+            const R u0 = U(c, line, q - 2), u1 = U(c, line, q - 1), u2 = U(c, line, q), u3 = U(c, line, q + 1),
+                    u4 = U(c, line, q + 2);
+            const int fl = use_switch ? monotone_flag<kExact>(double(u1), double(u2), double(u3)) : 0;
+            const int fl_next = __shfl_down(fl, 1);
+            double e = 0.0;
+            if (use_eta) {
+              e = eta_ratio<kExact>(double(u1), double(u2), double(u3), double(u4), eps_m);
+              if (use_switch && ((fl | fl_next) & 1)) e = 0.0;
+            }
+            const R eta_r = R(e), eta_l = __shfl_up(eta_r, 1);
+            R vm, vp;
+            if (eno) {
+              const int r = eno_stencil(double(u0), double(u1), double(u2), double(u3), double(u4));
+              vm = eno_minus<R>(r, u0, u1, u2, u3, u4, eta_r);
+              vp = eno_plus<R>(r, u0, u1, u2, u3, u4, eta_l);
+            } else {
+              R d0, d1, d2;
+              weight_denominators<R>(u0, u1, u2, u3, u4, eps, d0, d1, d2);
+              vm = weno_minus<R>(u0, u1, u2, u3, u4, eta_r, d0, d1, d2);
+              vp = weno_plus<R>(u0, u1, u2, u3, u4, eta_l, d0, d1, d2);
+            }
+            A[c] = vm;
+            B[c] = __shfl_down(vp, 1);
+          }
+          lf_flux<R, FLUX, M, 0>(A, B, alpha_x, speed_x, gamma, H);
+          if (lane < 63) {
+#pragma unroll
+            for (int c = 0; c < M; ++c) s_F[c][cid(line, lane - 1)] = H[c];
+          }
+        }
+      }
+    }
     // cell phase: flag and weight denominators of cells -1..LEN of every line (none in the
     // characteristic mode: its fields belong to an interface)
-    for (int w = tid; w < (CHAR || cross ? 0 : NPOS * LINES); w += BS) {
+    for (int w = tid; w < (CHAR || cross || rows ? 0 : NPOS * LINES); w += BS) {
       const int line = DIR == 0 ? w / NPOS : w % LINES;
       const int pos = DIR == 0 ? w % NPOS - 1 : w / LINES - 1;
       const int q = pos + 3;
@@ -250,9 +300,9 @@ __global__ __launch_bounds__(256) void stage2d_kernel(StageArgs a) {
           s_flag[c / 2][w] = (unsigned char)(s_flag[c / 2][w] | (fl << 4));
       }
     }
-    __syncthreads();
+    if (!rows) __syncthreads();  // rows is uniform over the workgroup
     // interface phase: pos+1/2 for pos = -1..LEN-1; the flux is stored at the left cell's index
-    for (int wi = tid; wi < (LEN + 1) * LINES; wi += BS) {
+    for (int wi = tid; wi < (rows ? 0 : (LEN + 1) * LINES); wi += BS) {
       const int line = DIR == 0 ? wi / (LEN + 1) : wi % LINES;
       const int pos = DIR == 0 ? wi % (LEN + 1) - 1 : wi / LINES - 1;
       const int q = pos + 3;

@@ -130,3 +130,66 @@ def test_every_2d_launch_shape_fp64(shape, recon, monkeypatch):
     assert np.array_equal(L, Lo)
     uo, _, _ = O.solve(_oracle_problem(w), w.u0, w.T, max_steps=3)
     assert np.array_equal(u, uo)
+
+
+def _burgers2d(n, ny, seed=7):
+    xc = (np.arange(n) + 0.5) / n
+    yc = (np.arange(ny) + 0.5) / ny
+    X, Y = np.meshgrid(xc, yc)
+    rng = np.random.default_rng(seed)
+    u0 = 0.2 + np.sin(2 * np.pi * X) * np.cos(2 * np.pi * Y) + 0.05 * rng.random((ny, n))
+    return I.Workload(name="b2", nx=n, ny=ny, dim=2, flux=I.BURGERS, u0=u0.reshape(-1), T=0.2, x0=0, x1=1,
+                      y0=0, y1=1, cfl=0.4)
+
+
+_ROW_CASES = ([(I.EULER, r, I.SWITCH_MONOTONE) for r in (I.RBF_WENO5, I.WENO5_JS, I.RBF_ENO3, I.ENO3)] +
+              [(I.BURGERS, r, sw) for r in (I.RBF_WENO5, I.WENO5_JS, I.RBF_ENO3, I.ENO3)
+               for sw in (I.SWITCH_MONOTONE, I.SWITCH_OFF)])
+
+
+@pytest.mark.parametrize("flux,recon,switch", _ROW_CASES)
+def test_row_wave_x_sweep_fp64(flux, recon, switch, monkeypatch):
+    """The 62 x 8 tile with per-interface denominators runs its x sweep one wave per row (lane
+    shuffles carry the next cell's flag, the previous interface's eta and the next cell's v^+):
+    every k = 3 scheme gives the oracle's bits on a ragged grid, with the switch on and (on the
+    scalar data; unswitched eta goes non-physical at the Euler quadrant jumps) off."""
+    _say(f"row-wave x sweep flux={flux} recon={recon} switch={switch}")
+    monkeypatch.setenv("NPW_TILE2D", "4")
+    if flux == I.EULER:
+        w = _quadrants(131, 131)
+        U = w.u0.reshape(4, 131, 131)[:, :37, :131].copy().reshape(-1)
+        w = w.with_(nx=131, ny=37, u0=U)
+    else:
+        w = _burgers2d(131, 37)
+    w = w.with_(recon=recon, switch_mode=switch)
+    with B.Solver(w.u0, **B.workload_params(w)) as s:
+        ls = s.launch_shape()
+        assert (ls["tile_x"], ls["tile_y"], ls["lds_shared"]) == (62, 8, 0)
+        L = s.rhs()
+        s.solve(w.T, max_steps=3)
+        u = s.read()
+    Lo, _ = O.rhs(_oracle_problem(w), w.u0)
+    assert np.array_equal(L, Lo)
+    uo, _, _ = O.solve(_oracle_problem(w), w.u0, w.T, max_steps=3)
+    assert np.array_equal(u, uo)
+
+
+@pytest.mark.parametrize("recon", [I.RBF_WENO5, I.RBF_ENO3])
+def test_row_wave_x_sweep_fp32(recon, monkeypatch):
+    """Float bulk: the one-wave-per-row x sweep (62 x 8) against the interface-per-thread sweep
+    (64 x 8, same per-interface arithmetic) and against the FP64 oracle."""
+    _say(f"row-wave x sweep fp32 recon={recon}")
+    w = _quadrants(131, 131).with_(recon=recon)
+    U = w.u0.reshape(4, 131, 131)[:, :37, :131].copy().reshape(-1)
+    w = w.with_(nx=131, ny=37, u0=U)
+    u32 = np.asarray(w.u0, np.float32)
+    out = {}
+    for shape in ("3", "4"):
+        monkeypatch.setenv("NPW_TILE2D", shape)
+        with B.Solver(u32, **B.workload_params(w, B.FP32)) as s:
+            s.solve(w.T, max_steps=5)
+            out[shape] = s.read().astype(np.float64)
+    assert np.max(np.abs(out["4"] - out["3"])) <= 1e-6
+    uo, _, _ = O.solve(_oracle_problem(w), u32.astype(np.float64), w.T, max_steps=5)
+    assert np.mean(np.abs(out["4"] - uo)) <= 1e-5
+    assert np.max(np.abs(out["4"] - uo)) <= 1e-3  # near the quadrant discontinuities
