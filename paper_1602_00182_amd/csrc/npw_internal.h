@@ -92,7 +92,8 @@ hipError_t launch_stage_f32(int flux, int ncomp, int block, const StageArgs& a, 
 // recomputed tiles, 64 x 12 and 64 x 16, do less halo work along y but hold more LDS; measured
 // slower on 2048^2 Euler: 211 and 251 us per stage against 193 us for 64 x 8.  Recomputed 63 x 8,
 // whose x sweep fills exactly 8 waves, measured the same as 64 x 8 (187.8-188.6 us); 127 x 4 took
-// 250 us.)
+// 250 us.  With the one-wave-per-row x sweep, a 62 x 16 tile on 512 threads took 160.4 us against
+// 153.5 us for 62 x 8.)
 constexpr int k2dShapes = 6;
 hipError_t launch_stage2d_f64(int flux, int ncomp, int shape, const StageArgs& a, hipStream_t s);
 hipError_t launch_stage2d_f32(int flux, int ncomp, int shape, const StageArgs& a, hipStream_t s);
