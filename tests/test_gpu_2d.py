@@ -193,3 +193,25 @@ def test_row_wave_x_sweep_fp32(recon, monkeypatch):
     uo, _, _ = O.solve(_oracle_problem(w), u32.astype(np.float64), w.T, max_steps=5)
     assert np.mean(np.abs(out["4"] - uo)) <= 1e-5
     assert np.max(np.abs(out["4"] - uo)) <= 1e-3  # near the quadrant discontinuities
+
+
+@pytest.mark.parametrize("n,ny,bc", [(5, 3, I.PERIODIC), (62, 8, I.TRANSMISSIVE), (63, 9, I.PERIODIC),
+                                     (124, 17, I.TRANSMISSIVE)])
+def test_row_wave_x_sweep_grid_edges_fp64(n, ny, bc, monkeypatch):
+    """The one-wave-per-row x sweep on a grid smaller than one tile (its rows wrap several times
+    through the periodic ghosts), on exactly one tile, one cell past a tile in each direction, and
+    on two by two tiles plus one row: the oracle's bits."""
+    _say(f"row-wave x sweep grid {n}x{ny} bc={bc}")
+    monkeypatch.setenv("NPW_TILE2D", "4")
+    w = _quadrants(max(n, ny), max(n, ny))
+    U = w.u0.reshape(4, w.ny, w.nx)[:, :ny, :n].copy().reshape(-1)
+    w = w.with_(nx=n, ny=ny, u0=U, bc=bc)
+    with B.Solver(w.u0, **B.workload_params(w)) as s:
+        assert (s.launch_shape()["tile_x"], s.launch_shape()["tile_y"]) == (62, 8)
+        L = s.rhs()
+        s.solve(w.T, max_steps=4)
+        u = s.read()
+    Lo, _ = O.rhs(_oracle_problem(w), w.u0)
+    assert np.array_equal(L, Lo)
+    uo, _, _ = O.solve(_oracle_problem(w), w.u0, w.T, max_steps=4)
+    assert np.array_equal(u, uo)
