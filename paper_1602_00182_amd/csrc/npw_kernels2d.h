@@ -30,6 +30,9 @@ __global__ __launch_bounds__(256) void stage2d_kernel(StageArgs a) {
   // one wave per row in the x sweep: cells -1..TX of a row fill a wave exactly (scalar flags and
   // per-interface denominators only)
   constexpr bool kRowWave = TX + 2 == 64 && !CHAR && !K2 && !SHARE;
+  // one wave per component in the y sweep (as many components as waves): each lane marches up
+  // one column of the tile
+  constexpr bool kColMarch = kRowWave && M == BS / 64;
   // per-cell flags (bit 0 switch, bits 1-2 ENO stencil) of two components share a byte
   __shared__ unsigned char s_flag[(M + 1) / 2][NC];
   __shared__ R s_den[SHARE ? M : 1][3][SHARE ? NC : 1];
@@ -194,6 +197,8 @@ __global__ __launch_bounds__(256) void stage2d_kernel(StageArgs a) {
   __syncthreads();
 
   R Lr[NOWN][M];  // L(u) of this thread's owned cells (x sweep, then + y sweep)
+  R usr[kColMarch ? NOWN : 1][M] = {};  // the owned cells' stage input, kept when s_u is reused
+  bool ycol = false;
 #pragma unroll
   for (int k = 0; k < NOWN; ++k)
 #pragma unroll
@@ -258,9 +263,86 @@ __global__ __launch_bounds__(256) void stage2d_kernel(StageArgs a) {
         }
       }
     }
+    // y sweep with one wave per component: wave c takes component c and lane x column x; the
+    // lane walks the column's cells j = -1..LEN, forming the flag and weight denominators of each
+    // cell and the eta and both edge values of each interface j - 1/2 once, with the window and the
+    // previous cell's values carried in registers.  v^- goes to s_F, v^+ to the staged tile's
+    // storage once every wave has finished reading it, and a flux pass combines the components.
+    // Same functions on the same operands as the two phases below.
+    if constexpr (DIR == 1 && kColMarch) {
+      ycol = !cross;
+      if (ycol) {
+        static_assert(M * NF <= M * WY * WX, "v+ fits in the staged tile");
+        const int c = tid >> 6, lx = tid & 63, x = lx < TX ? lx : TX - 1;
+        auto V = [&](int j) -> R { return s_u[c][j + 3][x + 3]; };  // cell j of column x, j = -3..LEN+2
+        R vp[LEN + 1];
+        int fl_prev = 0, r_prev = 0;
+        R d0p = R(0), d1p = R(0), d2p = R(0);
+#pragma unroll
+        for (int j = -1; j <= LEN; ++j) {
+          const R z = V(j - 3), ua = V(j - 2), ub = V(j - 1), uc = V(j), ud = V(j + 1), ue = V(j + 2);
+          const int fl = use_switch ? monotone_flag<kExact>(double(ub), double(uc), double(ud)) : 0;
+          int r = 0;
+          R d0 = R(0), d1 = R(0), d2 = R(0);
+          if (eno)
+            r = eno_stencil(double(ua), double(ub), double(uc), double(ud), double(ue));
+          else
+            weight_denominators<R>(ua, ub, uc, ud, ue, eps, d0, d1, d2);
+          if (j >= 0) {  // interface j - 1/2 between cells j - 1 and j
+            double e = 0.0;
+            if (use_eta) {
+              e = eta_ratio<kExact>(double(ua), double(ub), double(uc), double(ud), eps_m);
+              if (use_switch && ((fl_prev | fl) & 1)) e = 0.0;
+            }
+            const R eta = R(e);
+            R vm;
+            if (eno) {
+              vm = eno_minus<R>(r_prev, z, ua, ub, uc, ud, eta);
+              vp[j] = eno_plus<R>(r, ua, ub, uc, ud, ue, eta);
+            } else {
+              vm = weno_minus<R>(z, ua, ub, uc, ud, eta, d0p, d1p, d2p);
+              vp[j] = weno_plus<R>(ua, ub, uc, ud, ue, eta, d0, d1, d2);
+            }
+            if (lx < TX) s_F[c][cid(lx, j - 1)] = vm;
+          }
+          fl_prev = fl;
+          r_prev = r;
+          d0p = d0;
+          d1p = d1;
+          d2p = d2;
+        }
+#pragma unroll
+        for (int k = 0; k < NOWN; ++k) {
+          const int o = tid + k * BS;
+          if (o < TX * TY) {
+#pragma unroll
+            for (int cc = 0; cc < M; ++cc) usr[k][cc] = s_u[cc][o / TX + 3][o % TX + 3];
+          }
+        }
+        __syncthreads();  // every wave is done with s_u
+        R* vpb = &s_u[0][0][0];
+        if (lx < TX) {
+#pragma unroll
+          for (int j = 0; j <= LEN; ++j) vpb[c * NF + cid(lx, j - 1)] = vp[j];
+        }
+        __syncthreads();
+        for (int wi = tid; wi < (LEN + 1) * LINES; wi += BS) {
+          R A[M], B[M], H[M];
+#pragma unroll
+          for (int cc = 0; cc < M; ++cc) {
+            A[cc] = s_F[cc][wi];
+            B[cc] = vpb[cc * NF + wi];
+          }
+          lf_flux<R, FLUX, M, 1>(A, B, alpha_y, speed_y, gamma, H);
+#pragma unroll
+          for (int cc = 0; cc < M; ++cc) s_F[cc][wi] = H[cc];
+        }
+      }
+    }
+    const bool fused = rows || ycol;
     // cell phase: flag and weight denominators of cells -1..LEN of every line (none in the
     // characteristic mode: its fields belong to an interface)
-    for (int w = tid; w < (CHAR || cross || rows ? 0 : NPOS * LINES); w += BS) {
+    for (int w = tid; w < (CHAR || cross || fused ? 0 : NPOS * LINES); w += BS) {
       const int line = DIR == 0 ? w / NPOS : w % LINES;
       const int pos = DIR == 0 ? w % NPOS - 1 : w / LINES - 1;
       const int q = pos + 3;
@@ -300,9 +382,9 @@ __global__ __launch_bounds__(256) void stage2d_kernel(StageArgs a) {
           s_flag[c / 2][w] = (unsigned char)(s_flag[c / 2][w] | (fl << 4));
       }
     }
-    if (!rows) __syncthreads();  // rows is uniform over the workgroup
+    if (!fused) __syncthreads();  // rows and ycol are uniform over the workgroup
     // interface phase: pos+1/2 for pos = -1..LEN-1; the flux is stored at the left cell's index
-    for (int wi = tid; wi < (rows ? 0 : (LEN + 1) * LINES); wi += BS) {
+    for (int wi = tid; wi < (fused ? 0 : (LEN + 1) * LINES); wi += BS) {
       const int line = DIR == 0 ? wi / (LEN + 1) : wi % LINES;
       const int pos = DIR == 0 ? wi % (LEN + 1) - 1 : wi / LINES - 1;
       const int q = pos + 3;
@@ -428,7 +510,7 @@ __global__ __launch_bounds__(256) void stage2d_kernel(StageArgs a) {
 #pragma unroll
     for (int c = 0; c < M; ++c) {
       const R L = Lr[k][c];
-      const R us = s_u[c][y + 3][x + 3];
+      const R us = ycol ? usr[k][c] : s_u[c][y + 3][x + 3];  // s_u holds v^+ after a column march
       if (stage == 0)
         unew[c] = L;
       else
