@@ -7,6 +7,10 @@
 // stages the tile with a three-cell halo in LDS, runs the x sweep (flags, eta, reconstruction,
 // flux) over the TY rows, accumulates -dF/dx, runs the same sweep over the TX columns along y,
 // and applies the stage update.  The epilogue reduces alpha_x and alpha_y of the new state.
+// A sweep runs as a cell phase and an interface phase (one thread per interface), or, on
+// 62-wide tiles with k = 3 component-wise reconstruction, fused: along x one wave per row with
+// lane shuffles, along y (as many components as waves) one wave per component with each lane
+// walking a column, so every cell's quantities are formed once.
 #pragma once
 #include <type_traits>
 
