@@ -284,7 +284,7 @@ __global__ __launch_bounds__(256) void stage2d_kernel(StageArgs a) {
         R d0p = R(0), d1p = R(0), d2p = R(0);
 #pragma unroll
         for (int j = -1; j <= LEN; ++j) {
-          const R z = V(j - 3), ua = V(j - 2), ub = V(j - 1), uc = V(j), ud = V(j + 1), ue = V(j + 2);
+          const R ua = V(j - 2), ub = V(j - 1), uc = V(j), ud = V(j + 1), ue = V(j + 2);
           const int fl = use_switch ? monotone_flag<kExact>(double(ub), double(uc), double(ud)) : 0;
           int r = 0;
           R d0 = R(0), d1 = R(0), d2 = R(0);
@@ -293,6 +293,7 @@ __global__ __launch_bounds__(256) void stage2d_kernel(StageArgs a) {
           else
             weight_denominators<R>(ua, ub, uc, ud, ue, eps, d0, d1, d2);
           if (j >= 0) {  // interface j - 1/2 between cells j - 1 and j
+            const R z = V(j - 3);  // the left cell's farthest neighbour (staged rows start at j = -3)
             double e = 0.0;
             if (use_eta) {
               e = eta_ratio<kExact>(double(ua), double(ub), double(uc), double(ud), eps_m);
