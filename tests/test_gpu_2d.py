@@ -174,14 +174,28 @@ def test_row_wave_x_sweep_fp64(flux, recon, switch, monkeypatch):
     assert np.array_equal(u, uo)
 
 
-@pytest.mark.parametrize("recon", [I.RBF_WENO5, I.RBF_ENO3])
-def test_row_wave_x_sweep_fp32(recon, monkeypatch):
-    """Float bulk: the one-wave-per-row x sweep (62 x 8) against the interface-per-thread sweep
-    (64 x 8, same per-interface arithmetic) and against the FP64 oracle."""
-    _say(f"row-wave x sweep fp32 recon={recon}")
-    w = _quadrants(131, 131).with_(recon=recon)
-    U = w.u0.reshape(4, 131, 131)[:, :37, :131].copy().reshape(-1)
-    w = w.with_(nx=131, ny=37, u0=U)
+# Without the switch, eta = D3 / D1 is singular wherever D1 crosses zero, which the noisy Burgers
+# data does often (unswitched RBF-WENO5 reaches |u| ~ 4e3 in five steps): a unit of float
+# rounding then moves eta by O(1), and float results are not comparable.  The FP64 test covers
+# those cases bit for bit; here the RBF schemes run switched.
+_ROW_CASES_F32 = [k for k in _ROW_CASES if not (k[2] == I.SWITCH_OFF and k[1] in (I.RBF_WENO5, I.RBF_ENO3))]
+
+
+@pytest.mark.parametrize("flux,recon,switch", _ROW_CASES_F32)
+def test_row_wave_x_sweep_fp32(flux, recon, switch, monkeypatch):
+    """Float bulk: the fused sweeps of the 62 x 8 tile (one wave per row in x; for Euler one
+    wave per component in y) against the interface-per-thread sweeps (64 x 8: the same
+    functions, but fused multiply-adds may be formed differently, so results agree to about one
+    unit in the last place, and an ENO stencil choice may flip where they differ; hence the
+    comparison in the mean) and against the FP64 oracle."""
+    _say(f"fused sweeps fp32 flux={flux} recon={recon} switch={switch}")
+    if flux == I.EULER:
+        w = _quadrants(131, 131)
+        U = w.u0.reshape(4, 131, 131)[:, :37, :131].copy().reshape(-1)
+        w = w.with_(nx=131, ny=37, u0=U)
+    else:
+        w = _burgers2d(131, 37)
+    w = w.with_(recon=recon, switch_mode=switch)
     u32 = np.asarray(w.u0, np.float32)
     out = {}
     for shape in ("3", "4"):
@@ -189,10 +203,11 @@ def test_row_wave_x_sweep_fp32(recon, monkeypatch):
         with B.Solver(u32, **B.workload_params(w, B.FP32)) as s:
             s.solve(w.T, max_steps=5)
             out[shape] = s.read().astype(np.float64)
-    assert np.max(np.abs(out["4"] - out["3"])) <= 1e-6
+    scale = max(1.0, float(np.max(np.abs(out["3"]))))
+    assert np.mean(np.abs(out["4"] - out["3"])) <= 1e-6 * scale
     uo, _, _ = O.solve(_oracle_problem(w), u32.astype(np.float64), w.T, max_steps=5)
-    assert np.mean(np.abs(out["4"] - uo)) <= 1e-5
-    assert np.max(np.abs(out["4"] - uo)) <= 1e-3  # near the quadrant discontinuities
+    assert np.mean(np.abs(out["4"] - uo)) <= 1e-5 * scale
+    assert np.max(np.abs(out["4"] - uo)) <= 1e-3 * scale  # near the quadrant discontinuities
 
 
 @pytest.mark.parametrize("n,ny,bc", [(5, 3, I.PERIODIC), (62, 8, I.TRANSMISSIVE), (63, 9, I.PERIODIC),
