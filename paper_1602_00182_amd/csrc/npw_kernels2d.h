@@ -223,9 +223,10 @@ __global__ __launch_bounds__(256) void stage2d_kernel(StageArgs a) {
     // x sweep with one wave per row, for tiles whose staged row holds cells -1..TX in exactly one
     // wave: lane l takes cell p = l - 1 and forms its flag, weight denominators, eta_{p+1/2} and
     // both edge values once; the next cell's flag, eta_{p-1/2} and v^+_{p+1/2} arrive by lane
-    // shuffles.  Same functions on the same operands as the two phases below, so the fluxes are
-    // identical; the separate flag pass and its barrier go away, and so does the second
-    // denominator set of every interface.
+    // shuffles.  Same functions on the same operands as the two phases below: the double bulk's
+    // fluxes are identical bit for bit (the float bulk's up to how multiply-adds are fused); the
+    // separate flag pass and its barrier go away, and so does the second denominator set of every
+    // interface.
     bool rows = false;
     if constexpr (DIR == 0 && kRowWave) {
       rows = !cross;
@@ -272,7 +273,8 @@ __global__ __launch_bounds__(256) void stage2d_kernel(StageArgs a) {
     // cell and the eta and both edge values of each interface j - 1/2 once, with the window and the
     // previous cell's values carried in registers.  v^- goes to s_F, v^+ to the staged tile's
     // storage once every wave has finished reading it, and a flux pass combines the components.
-    // Same functions on the same operands as the two phases below.
+    // Same functions on the same operands as the two phases below (bit for bit in the double
+    // bulk, up to how multiply-adds are fused in the float bulk).
     if constexpr (DIR == 1 && kColMarch) {
       ycol = !cross;
       if (ycol) {
