@@ -211,14 +211,15 @@ def test_row_wave_x_sweep_fp32(flux, recon, switch, monkeypatch):
 
 
 @pytest.mark.parametrize("n,ny,bc", [(5, 3, I.PERIODIC), (62, 8, I.TRANSMISSIVE), (63, 9, I.PERIODIC),
-                                     (124, 17, I.TRANSMISSIVE)])
+                                     (124, 17, I.TRANSMISSIVE), (1, 7, I.PERIODIC), (9, 1, I.TRANSMISSIVE),
+                                     (1, 1, I.PERIODIC), (2, 2, I.TRANSMISSIVE)])
 def test_row_wave_x_sweep_grid_edges_fp64(n, ny, bc, monkeypatch):
-    """The one-wave-per-row x sweep on a grid smaller than one tile (its rows wrap several times
-    through the periodic ghosts), on exactly one tile, one cell past a tile in each direction, and
-    on two by two tiles plus one row: the oracle's bits."""
+    """The fused sweeps on a grid smaller than one tile (its rows wrap several times through the
+    periodic ghosts), on exactly one tile, one cell past a tile in each direction, on two by two
+    tiles plus one row, and on degenerate grids one cell wide or tall: the oracle's bits."""
     _say(f"row-wave x sweep grid {n}x{ny} bc={bc}")
     monkeypatch.setenv("NPW_TILE2D", "4")
-    w = _quadrants(max(n, ny), max(n, ny))
+    w = _quadrants(max(n, ny, 4), max(n, ny, 4))
     U = w.u0.reshape(4, w.ny, w.nx)[:, :ny, :n].copy().reshape(-1)
     w = w.with_(nx=n, ny=ny, u0=U, bc=bc)
     with B.Solver(w.u0, **B.workload_params(w)) as s:
