@@ -660,18 +660,19 @@ __device__ __forceinline__ R spectral_radius(const R* U, R speed, R gamma, int& 
 
 // SSP-RK3 stage combination (Section 5.1) of u^n, the stage input v and its increment dt L(v):
 //   stage 1: v + dt L;  stage 2: 3/4 u^n + 1/4 (v + dt L);  stage 3: 1/3 u^n + 2/3 (v + dt L).
-// The double bulk evaluates exactly these expressions.  The float bulk evaluates the same values
-// as v + (w (u^n - v) + (1 - w) dt L) with w = 3/4 or 1/3.  In float, fl(1/3) + fl(2/3) exceeds 1
-// by 3e-8, so the written form would scale the state by that much every step: a bias that grows
-// linearly (about 1e-8 per step in L1 on sin(pi x)).  In the rearranged form the weights only
-// multiply O(dt) quantities (u^n - v is exact for nearby floats), and one rounding of v + (...)
-// remains.
+// Stage 3 is evaluated as v + (w (u^n - v) + (1 - w) dt L) with w = 1/3 in both precisions:
+// fl(1/3) + fl(2/3) is 1 - 2^-54 in double and 1 + 3e-8 in float, so the written form would
+// scale the cell-average sum by that factor every step (a drift of 2.6e-12 over a 47 000-step
+// double solve; about 1e-8 per step in L1 for float on sin(pi x)).  In the rearranged form the
+// weights multiply only quantities whose sums over a periodic grid vanish, and one rounding of
+// v + (...) remains.  The double bulk takes stage 2 as written (3/4 and 1/4 are exact), with
+// the same operation order as the oracle; the float bulk rearranges stage 2 the same way.
 template <typename R>
 __device__ __forceinline__ R rk3_combine(int stage, R un, R v, R dtl) {
   if constexpr (sizeof(R) == 8) {
     if (stage == 1) return v + dtl;
     if (stage == 2) return R(0.75) * un + R(0.25) * (v + dtl);
-    return R(1.0 / 3.0) * un + R(2.0 / 3.0) * (v + dtl);
+    return v + (R(1.0 / 3.0) * (un - v) + R(2.0 / 3.0) * dtl);
   } else {
     if (stage == 1) return v + dtl;
     if (stage == 2) return v + (R(0.75) * (un - v) + R(0.25) * dtl);

@@ -185,14 +185,58 @@ def test_monotone_flag_matches_quadratic_extremum():
     for _ in range(3000):
         a, b, c = (int(v) for v in rng.integers(-20, 21, size=3))
         xs = _quadratic_extremum(a, b, c)
-        if xs is not None and (xs == 0 or xs == 3):
-            continue  # exact tie: outside the strict inequality by definition
+        # Exact ties (extremum on the window's outer edge) fail the strict inequalities of eq.
+        # (adaptation) and count as monotone; they are kept in the draw.
         expect = int(xs is not None and 0 < xs < 3)
         n_flag += expect
         if O.monotone_flag(float(a), float(b), float(c)) != expect:
             mismatches += 1
     assert mismatches == 0
     assert 300 < n_flag < 2950  # both outcomes well represented
+
+
+def _tie_windows():
+    """Integer windows whose quadratic has its extremum exactly at x_p = 0 or x_p = 3 dx, the
+    outer edges x_{j-3/2}, x_{j+3/2} of the stencil (found with rational arithmetic)."""
+    out = []
+    for a in range(-6, 7):
+        for b in range(-6, 7):
+            for c in range(-6, 7):
+                xs = _quadratic_extremum(a, b, c)
+                if xs is not None and (xs == 0 or xs == 3):
+                    out.append((a, b, c, int(xs)))
+    return out
+
+
+def test_monotone_flag_ties_are_monotone():
+    """Section 4 prints strict inequalities, 0 < x_p < 3 dx: an extremum exactly on the stencil's
+    outer edge leaves p monotone inside it, so the window is not flagged.  Just inside either edge
+    it is flagged."""
+    ties = _tie_windows()
+    assert sum(1 for t in ties if t[3] == 0) > 20 and sum(1 for t in ties if t[3] == 3) > 20
+    for a, b, c, _ in ties:
+        assert O.monotone_flag(float(a), float(b), float(c)) == 0, (a, b, c)
+    assert O.monotone_flag(0.0, 1.0, 3.0) == 0  # x_p = 0
+    assert O.monotone_flag(3.0, 1.0, 0.0) == 0  # x_p = 3 dx
+    assert O.monotone_flag(0.0, 1.0, 3.001) == 1  # x_p = 0.001/1.001: just above 0
+    assert O.monotone_flag(3.001, 1.0, 0.0) == 1  # x_p = 3.002/1.001: just below 3 dx
+
+
+def test_switch_leaves_eta_at_tie_windows():
+    """Through the interface states: a line whose cells form x_p = 0 and x_p = 3 dx windows keeps
+    the shape parameter at the interfaces next to them (switch on), like the switch-off line."""
+    line = np.array([5.0, 4.0, 4.5, 0.0, 1.0, 3.0, 3.5, 3.0, 1.0, 0.0, 0.25, 0.5, 1.0, 1.5, 2.0, 2.5])
+    # windows centred on cells 4 (0, 1, 3) and 8 (3, 1, 0) are the ties
+    assert O.monotone_flag(*line[3:6]) == 0 and O.monotone_flag(*line[7:10]) == 0
+    on = O.line_states(O.Problem(nx=line.size, flux=O.BURGERS), line)
+    off = O.line_states(O.Problem(nx=line.size, flux=O.BURGERS, switch_mode=O.SWITCH_OFF), line)
+    for cell in (4, 8):
+        for iface in (cell, cell + 1):  # interfaces cell-1/2 and cell+1/2 (index i+1 for i+1/2)
+            others = [q for q in (iface - 1, iface) if q != cell]  # the other adjacent cell
+            if any(O.monotone_flag(*line[q - 1:q + 2]) for q in others):
+                continue
+            assert on[3][iface] == 0 and on[2][iface] == off[2][iface] != 0.0, (cell, iface)
+            assert on[0][iface] == off[0][iface] and on[1][iface] == off[1][iface]
 
 
 def test_monotone_flag_linear_and_constant_windows():

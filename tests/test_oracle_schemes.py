@@ -172,6 +172,73 @@ def test_periodic_conservation():
     assert abs(u.sum() - w.u0.sum()) <= 1e-13 * np.abs(w.u0).sum()
 
 
+@pytest.mark.parametrize("flux", [O.BURGERS, O.ADVECTION])
+def test_periodic_conservation_over_many_steps(flux):
+    """The finite-volume update conserves the sum of the cell averages exactly (Section 5.1,
+    eq. PDE1 with periodic data), so 20 000 RK3 steps must keep it to 1e-13 relative.  A stage
+    combination whose weights do not sum to one in double (fl(1/3) + fl(2/3) = 1 - 2^-54) loses
+    about 1.1e-12 over this run."""
+    w = I.burgers_noisy(n=64, seed=8)
+    pb = O.Problem(nx=64, flux=flux, cfl=0.5)
+    u, _, ns = O.solve(pb, w.u0, 1e9, max_steps=20000)
+    assert ns == 20000
+    s0, s1 = math.fsum(w.u0), math.fsum(u)
+    assert abs(s1 - s0) <= 1e-13 * math.fsum(np.abs(w.u0))
+
+
+def _pad_with_edge_copies(u, m, g=3):
+    """Component-major state of n cells -> n + 2g cells: g copies of each edge cell outside."""
+    n = u.size // m
+    comps = [u[c * n:(c + 1) * n] for c in range(m)]
+    return np.concatenate([np.concatenate([np.full(g, v[0]), v, np.full(g, v[-1])]) for v in comps])
+
+
+_GHOST_CASES = [
+    ("rbf_weno5", dict(flux=O.BURGERS, recon=O.RBF_WENO5)),
+    ("rbf_eno3", dict(flux=O.BURGERS, recon=O.RBF_ENO3)),
+    ("rbf_weno3", dict(flux=O.BURGERS, recon=O.RBF_WENO3)),
+    ("euler", dict(flux=O.EULER, ncomp=3)),
+    ("euler_char", dict(flux=O.EULER, ncomp=3, charwise=1)),
+]
+
+
+@pytest.mark.parametrize("name,kw", _GHOST_CASES, ids=[c[0] for c in _GHOST_CASES])
+def test_transmissive_ghosts_are_copies_of_the_edge_cell(name, kw):
+    """A transmissive line gives exactly the interface states and rhs of the same line padded by
+    hand with three copies of each edge cell and run as the interior of a longer periodic line
+    (no interface of the original line reaches the periodic wrap).  Mirrored ghosts, or any other
+    extension, change the three interfaces next to each boundary."""
+    n, g = 24, 3
+    m = kw.get("ncomp", 1)
+    rng = np.random.default_rng(17)
+    if m == 1:
+        u = 1.0 + 0.5 * rng.standard_normal(n)
+    else:
+        rho = 1.0 + 0.3 * rng.random(n)
+        vel = 0.4 * rng.standard_normal(n)
+        pr = 1.0 + 0.3 * rng.random(n)
+        u = I.euler_prim_to_cons(rho, vel, pr).reshape(-1)
+    ext = _pad_with_edge_copies(u, m, g)
+    # unit cells in both problems, so dx = 1 exactly and the rhs compares bit for bit
+    pt = O.Problem(nx=n, bc=O.TRANSMISSIVE, x0=0.0, x1=float(n), **kw)
+    pp = O.Problem(nx=n + 2 * g, bc=O.PERIODIC, x0=-float(g), x1=float(n + g), **kw)
+    if m == 1:
+        a = O.line_states(pt, u)
+        b = O.line_states(pp, ext)
+        for k in range(2):  # v^-, v^+ at interfaces i+1/2, i = -1..n-1
+            np.testing.assert_array_equal(a[k], b[k][g:g + n + 1])
+    La, _ = O.rhs(pt, u)
+    Lb, _ = O.rhs(pp, ext)
+    Lb = Lb.reshape(m, n + 2 * g)[:, g:g + n].reshape(-1)
+    np.testing.assert_array_equal(La, Lb)
+    # the boundary interfaces really depend on the ghosts: mirrored ghosts differ there
+    mir = np.concatenate([np.concatenate([v[g - 1::-1], v, v[:-g - 1:-1]])
+                          for v in u.reshape(m, n)])
+    Lm, _ = O.rhs(pp, mir)
+    Lm = Lm.reshape(m, n + 2 * g)[:, g:g + n]
+    assert np.any(Lm[:, :g] != La.reshape(m, n)[:, :g]) and np.any(Lm[:, -g:] != La.reshape(m, n)[:, -g:])
+
+
 @pytest.mark.parametrize("flux,ncomp,state", [(O.BURGERS, 1, [0.7]), (O.ADVECTION, 1, [-1.3]),
                                               (O.EULER, 3, [0.9, 0.3, 2.1])])
 def test_constant_state_has_zero_rhs(flux, ncomp, state):
