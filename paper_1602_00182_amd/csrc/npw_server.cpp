@@ -56,7 +56,7 @@ struct Pool {
   InstDev* h_pin = nullptr;
   Tile* d_tiles = nullptr;
   int* d_ntiles = nullptr;
-  void* d_check = nullptr;    // one state-check partial record
+  void* d_check = nullptr;    // state-check partial records (kCheckMaxG)
   int tile_cap = 0;
   std::vector<int> slot_req;  // request index (into server order) per slot, -1 if free
   std::vector<uint64_t> slot_id;
@@ -67,6 +67,10 @@ struct Pool {
 
 constexpr int kBlock = 256;
 constexpr int kGrid = 2048;  // workgroups of a pool launch (grid-stride over its tiles)
+constexpr int kCheckMaxG = 512;  // state-check workgroups of one request: one per 16 Ki cells, at most this
+
+int check_groups(long long cells) { return (int)std::min<long long>(kCheckMaxG, std::max<long long>(1, cells / 16384)); }
+
 
 // Free-list allocator over [0, cap) elements (first fit, coalescing).
 struct Arena {
@@ -135,6 +139,16 @@ namespace {
 
 int pool_of(const npw_params* p) {  // advection 0, Burgers 1, Euler 2, Euler characteristic-wise 3
   return p->flux == NPW_EULER && p->variables == NPW_CHARACTERISTIC ? 3 : p->flux;
+}
+
+// State check of one request (alpha, validity, FP64 sums of its current state) on its pool's
+// stream.  Checks on one stream run in order, so they share the pool's partial records.
+hipError_t launch_check(const npw_server* s, const Pool& pl, int slot, long long cells) {
+  return s->precision == NPW_FP64
+             ? npw::launch_init_f64(pl.flux, pl.ncomp, pl.d_inst + slot, 1, s->P0, s->P1, nullptr, pl.d_check,
+                                    check_groups(cells), pl.stream)
+             : npw::launch_init_f32(pl.flux, pl.ncomp, pl.d_inst + slot, 1, s->P0, s->P1, nullptr, pl.d_check,
+                                    check_groups(cells), pl.stream);
 }
 
 hipError_t launch_stage(const npw_server* s, int flux, int ncomp, const StageArgs& a, hipStream_t st) {
@@ -257,8 +271,15 @@ InstDev make_slot(const Request& r, int par) {
   return d;
 }
 
-// Admit queued requests in FIFO order while slots and arena space allow.
+// Admit queued requests in FIFO order while slots and arena space allow.  Every admitted
+// request's state and record are copied and checked (alpha, validity, FP64 sums) on its pool's
+// stream; one synchronization at the end covers all of them.
 int admit(npw_server* s) {
+  std::vector<size_t> admitted;
+  std::vector<InstDev> staged;
+  staged.reserve(s->queue.size());  // the copies below read these records until the final sync
+  bool used[4] = {false, false, false, false};
+  int rc = NPW_OK;
   while (!s->queue.empty()) {
     Request& r = s->reqs[s->queue.front()];
     Pool& pl = s->pools[r.pool];
@@ -268,9 +289,9 @@ int admit(npw_server* s) {
         slot = b;
         break;
       }
-    if (slot < 0) return NPW_OK;
+    if (slot < 0) break;
     size_t off = 0;
-    if (!s->arena.alloc(r.len, &off)) return NPW_OK;
+    if (!s->arena.alloc(r.len, &off)) break;
     r.off = off;
     r.slot = slot;
     r.state = 1;
@@ -278,21 +299,27 @@ int admit(npw_server* s) {
     pl.slot_req[slot] = (int)s->queue.front();
     pl.slot_id[slot] = r.id;
     s->queue.pop_front();
-    char* dst = static_cast<char*>(pl.par ? s->P1 : s->P0) + off * s->esize;
-    HIP_TRY(hipMemcpyAsync(dst, r.u0.data(), r.len * s->esize, hipMemcpyHostToDevice, pl.stream));
-    InstDev d = make_slot(r, pl.par);
-    HIP_TRY(hipMemcpyAsync(pl.d_inst + slot, &d, sizeof d, hipMemcpyHostToDevice, pl.stream));
-    hipError_t e = s->precision == NPW_FP64 ? npw::launch_init_f64(pl.flux, pl.ncomp, pl.d_inst + slot, 1, s->P0,
-                                                                   s->P1, nullptr, pl.d_check, 1, pl.stream)
-                                            : npw::launch_init_f32(pl.flux, pl.ncomp, pl.d_inst + slot, 1, s->P0,
-                                                                   s->P1, nullptr, pl.d_check, 1, pl.stream);
-    if (e != hipSuccess) return NPW_EHIP;
-    HIP_TRY(hipStreamSynchronize(pl.stream));  // the host copy of the slot goes out of scope
-    r.u0.clear();
-    r.u0.shrink_to_fit();
+    admitted.push_back(pl.slot_req[slot]);
+    used[r.pool] = true;
     pl.dirty = true;
+    char* dst = static_cast<char*>(pl.par ? s->P1 : s->P0) + off * s->esize;
+    staged.push_back(make_slot(r, pl.par));
+    if (hipMemcpyAsync(dst, r.u0.data(), r.len * s->esize, hipMemcpyHostToDevice, pl.stream) != hipSuccess ||
+        hipMemcpyAsync(pl.d_inst + slot, &staged.back(), sizeof(InstDev), hipMemcpyHostToDevice, pl.stream) !=
+            hipSuccess ||
+        launch_check(s, pl, slot, r.p.nx) != hipSuccess) {
+      rc = NPW_EHIP;
+      break;
+    }
   }
-  return NPW_OK;
+  // the host copies of the states and records go out of scope after this
+  for (int k = 0; k < 4; ++k)
+    if (used[k] && hipStreamSynchronize(s->pools[k].stream) != hipSuccess) rc = NPW_EHIP;
+  for (size_t i : admitted) {
+    s->reqs[i].u0.clear();
+    s->reqs[i].u0.shrink_to_fit();
+  }
+  return rc;
 }
 
 void fill_stats_from(const InstDev& h, npw_stats* st) {
@@ -305,20 +332,52 @@ void fill_stats_from(const InstDev& h, npw_stats* st) {
   st->err_stage = h.err_stage;
 }
 
-// Copy out and free every request of the pool that reached its T or failed.
+// Copy out and free every request of the pool that reached its T or failed.  As a solo solve
+// does when it stops, the state check runs on each finishing request's final state (for a failed
+// request: its last good state, with the control word put back at that step) so that the alpha
+// and FP64 sums it reports are those of the state it returns.
 int retire(npw_server* s, Pool& pl) {
-  bool any = false;
+  std::vector<int> fin;
   for (int b = 0; b < s->max_slots; ++b) {
     if (pl.slot_req[b] < 0) continue;
-    Request& r = s->reqs[pl.slot_req[b]];
+    const Request& r = s->reqs[pl.slot_req[b]];
     const InstDev& h = pl.h_pin[b];
     const bool failed = h.err != 0;
     const bool done = !failed && !(r.T - h.ctl[0].t > 1e-12 * std::max(1.0, std::fabs(r.T)));
-    if (!failed && !done) continue;
-    const int home = failed ? h.err_home : h.ctl[0].home;
+    if (failed || done) fin.push_back(b);
+  }
+  if (fin.empty()) return NPW_OK;
+  std::vector<Ctl> back(fin.size());  // read by the copies below until the synchronization
+  for (size_t k = 0; k < fin.size(); ++k) {
+    const int b = fin[k];
+    const InstDev& h = pl.h_pin[b];
+    const Request& r = s->reqs[pl.slot_req[b]];
+    if (h.err) {
+      Ctl& c = back[k];
+      c.t = h.err_t;
+      c.dt = 0.0;
+      c.n = h.err_n;
+      c.active = 0;
+      c.home = h.err_home;
+      HIP_TRY(hipMemcpyAsync(reinterpret_cast<char*>(pl.d_inst + b) + offsetof(InstDev, ctl), &c, sizeof(Ctl),
+                             hipMemcpyHostToDevice, pl.stream));
+    }
+    HIP_TRY(launch_check(s, pl, b, r.p.nx));
+    HIP_TRY(hipMemcpyAsync(pl.h_pin + b, pl.d_inst + b, sizeof(InstDev), hipMemcpyDeviceToHost, pl.stream));
+  }
+  for (int b : fin) {
+    Request& r = s->reqs[pl.slot_req[b]];
+    const int home = pl.h_pin[b].err ? pl.h_pin[b].err_home : pl.h_pin[b].ctl[0].home;
     r.result.resize(r.len * s->esize);
     const char* src = static_cast<const char*>(home ? s->P1 : s->P0) + r.off * s->esize;
     HIP_TRY(hipMemcpyAsync(r.result.data(), src, r.len * s->esize, hipMemcpyDeviceToHost, pl.stream));
+  }
+  HIP_TRY(hipStreamSynchronize(pl.stream));
+  const double now = now_s();
+  for (int b : fin) {
+    Request& r = s->reqs[pl.slot_req[b]];
+    const InstDev& h = pl.h_pin[b];
+    const bool failed = h.err != 0;
     fill_stats_from(h, &r.stats);
     if (failed) {
       r.stats.t = h.err_t;
@@ -326,15 +385,11 @@ int retire(npw_server* s, Pool& pl) {
     }
     r.err = h.err;
     r.state = failed ? 3 : 2;
-    r.t_done = now_s();
+    r.t_done = now;
     s->arena.release(r.off, r.len);
     pl.slot_req[b] = -1;
-    any = true;
   }
-  if (any) {
-    HIP_TRY(hipStreamSynchronize(pl.stream));
-    pl.dirty = true;
-  }
+  pl.dirty = true;
   return NPW_OK;
 }
 
@@ -400,7 +455,7 @@ static int npw_server_create_impl(size_t hbm_budget_bytes, int32_t max_slots, in
          hipMalloc(&pl.d_inst, sizeof(InstDev) * max_slots) == hipSuccess &&
          hipMalloc(&pl.d_tiles, sizeof(Tile) * pl.tile_cap) == hipSuccess &&
          hipMalloc(&pl.d_ntiles, sizeof(int)) == hipSuccess &&
-         hipMalloc(&pl.d_check, npw::kCheckPartialBytes) == hipSuccess &&
+         hipMalloc(&pl.d_check, (size_t)npw::kCheckPartialBytes * kCheckMaxG) == hipSuccess &&
          hipHostMalloc(&pl.h_pin, sizeof(InstDev) * max_slots, hipHostMallocDefault) == hipSuccess;
     if (ok) {
       // idle slots: T = t = 0, so every launch skips them

@@ -6,6 +6,7 @@ import numpy as np
 import pytest
 
 import oracle as O
+from conftest import assert_fp32_close, check_sums, smooth_cells
 from paper_1602_00182_amd import binding as B
 from paper_1602_00182_amd import inputs as I
 
@@ -42,6 +43,7 @@ def test_euler_batch_matches_single_and_oracle(prec):
         got = [bt.read(b) for b in range(len(ws))]
     assert rc == B.OK
     for b, w in enumerate(ws):
+        check_sums(stats[b], got[b], 3, w.dx)
         with B.Solver(states[b], **B.workload_params(w, prec)) as s:
             st = s.solve(T[b])
             alone = s.read()
@@ -118,6 +120,9 @@ def test_full_size_riemann_batch_sampled_fp32():
         uo, _, _ = O.solve(_oracle_problem(w), states[b].astype(np.float64), w.T, max_steps=25)
         # Riemann data: the jump makes a few cells sensitive to rounding (L1 bound, as for Sod)
         assert np.mean(np.abs(got[b] - uo)) <= 1e-4, b
+        # element-wise 1e-5 (relative above 1) away from the waves
+        assert_fp32_close(got[b], uo, 3, smooth_cells(uo, 3, (w.nx,)))
+        check_sums(stats[b], got[b], 3, w.dx)
         with B.Solver(states[b], **B.workload_params(w, B.FP32)) as s:
             s.solve(w.T, 25)
             assert np.array_equal(s.read(), got[b]), b

@@ -6,6 +6,7 @@ import numpy as np
 import pytest
 
 import oracle as O
+from conftest import check_sums
 from paper_1602_00182_amd import binding as B
 from paper_1602_00182_amd import inputs as I
 
@@ -51,6 +52,9 @@ def test_results_identical_alone_and_in_the_mix(prec):
                 alone = s.read()
             assert st["nsteps"] == st1["nsteps"]
             assert np.array_equal(out, alone), rid
+            # the reported sums are those of the final state, as for the solo solve
+            check_sums(st, out, w.ncomp, w.dx)
+            assert st["mass"] == st1["mass"] and st["alpha"][0] == st1["alpha"][0]
             if prec == B.FP64 and w.nx <= 2000:
                 pb = O.Problem(nx=w.nx, flux=w.flux, ncomp=w.ncomp, bc=w.bc, cfl=w.cfl, gamma=w.gamma)
                 uo, _, _ = O.solve(pb, w.u0, w.T)
@@ -69,6 +73,7 @@ def test_failing_request_does_not_poison_others():
         _drain(srv, ids + [bad_id])
         out, st, rc = srv.poll(bad_id)
         assert rc == B.ENONFINITE and np.all(np.isfinite(out))
+        check_sums(st, out, 1, bad.dx)  # the sums of the last good state it returns
         for rid, w in zip(ids, good):
             out, st, rc = srv.poll(rid)
             assert rc == B.OK
