@@ -1,19 +1,20 @@
 """Benchmark of the non-polynomial WENO5 solver on one MI355X.
 
-Default workload (the headline): 1D Burgers u_t + (u^2/2)_x = 0, periodic on [-1, 1],
-N = 65536 cells, u0 = 0.5 + sin(pi x) + seeded U(-1e-3, 1e-3) noise, global Lax-Friedrichs,
-SSP-RK3 at CFL 0.5 to T = 1.5/pi (past shock formation, ~47k RK steps), RBF-WENO5 with the
-monotone switch, float bulk with double eta/switch.  One benchmark "step" is one whole solve
-from the initial state (the state is reset from a resident device copy).
+Default workload (the headline, the largest single-GPU configuration): 2D Euler dimension by
+dimension (Section 7, eq. 2DIntegral, one midpoint point per face) on 2048 x 2048 cells of
+[0,1]^2, four seeded constant quadrant states split at (0.5, 0.5), transmissive, gamma = 1.4,
+SSP-RK3 at CFL 0.4 to T = 0.25 (about 10^4 RK steps), RBF-WENO5 with the monotone switch, float
+bulk with double eta/switch.  One benchmark "step" is one whole solve from the initial state (the
+state is reset from a resident device copy).
 value = cells * 3 stages * RK steps * solves / wall seconds (cell-updates per RK stage).
 
-Other workloads (--workload): euler2d (2048^2 four-quadrant 2D Euler to T = 0.25), euler_batch
-(4096 Riemann problems, N in [256, 4096], to T = 0.2), serving (a Poisson trace through the
-continuous-batching loop, compared with one solve at a time), advection (sin(pi x) at N = 65536
-to T = 0.5) and advection2d (sin(2 pi (x + y)) on 2048^2 to T = 0.25), the paper's smooth test
-problems at the headline's sizes, on which the k = 2 and Section 6 reconstructions are defined
-everywhere (their shape parameter is singular where a solution with non-zero curvature crosses
-zero).  --recon and --variables pick the reconstruction.
+Other workloads (--workload): burgers (1D Burgers N = 65536, 0.5 + sin(pi x) + seeded noise, to
+T = 1.5/pi), euler_batch (4096 Riemann problems, N in [256, 4096], to T = 0.2), serving (a Poisson
+trace through the continuous-batching loop, compared with one solve at a time), advection (sin(pi x)
+at N = 65536 to T = 0.5) and advection2d (sin(2 pi (x + y)) on 2048^2 to T = 0.25), the paper's
+smooth test problems at the headline's sizes, on which the k = 2 and Section 6 reconstructions are
+defined everywhere (their shape parameter is singular where a solution with non-zero curvature
+crosses zero).  --recon and --variables pick the reconstruction.
 
 Prints one JSON line.  Only one GPU: --gpus N > 1 exits with a message.
 """
@@ -33,6 +34,14 @@ sys.path.insert(0, ROOT)
 import numpy as np  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
+# FP32 vector peak without packed-FP32 instructions (which this build disables): 256 CUs x 4 SIMDs
+# x 16 lanes x 2 flops per FMA x 2.4 GHz.  The published 157.3 TFLOP/s counts packed FMAs.
+ALU_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
+# Algorithmic FP32 flops of one scalar reconstruction + flux + update along one direction, per cell
+# and RK stage (smoothness indicators 21, substencil values 42, weights ~30, combination 6, LF flux
+# ~8, update ~5, switch ~8), and the Euler equation of state per cell and direction (~30, one sqrt).
+FLOPS_SCALAR_SWEEP = 130.0
+FLOPS_EULER_EOS = 30.0
 # Algorithmic HBM element accesses per cell, component and RK stage: stage 1 reads u^n and
 # writes u^(1); stages 2 and 3 read u^n and the stage input and write the output.
 ACCESSES_PER_CELL_STAGE = 8.0 / 3.0
@@ -115,21 +124,47 @@ def counter_valu(kernel: str):
     return None
 
 
+def alg_flops_per_cell_stage(w) -> float:
+    """Algorithmic FP32 flops per cell and RK stage: every component reconstructed along every
+    direction, plus the equation of state per direction for Euler."""
+    per_dir = w.ncomp * FLOPS_SCALAR_SWEEP + (FLOPS_EULER_EOS if w.flux == 2 else 0.0)
+    return w.dim * per_dir
+
+
+def host_description() -> dict:
+    """Host CPU model and core counts (the oracle baseline runs on these cores)."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"cpu_model": model, "nproc": os.cpu_count(), "affinity": len(os.sched_getaffinity(0))}
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None,
                     help="timed whole solves (default: 20 for burgers and advection, so p50/p99 rest on 20 "
-                         "samples; 3 for advection2d; 2 for euler_batch; 1 for euler2d, whose solve takes ~9 s)")
+                         "samples; 3 for euler2d and advection2d; 2 for euler_batch)")
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", choices=["burgers", "advection", "euler2d", "advection2d", "euler_batch", "serving"],
-                    default="burgers")
+                    default="euler2d")
     ap.add_argument("--precision", choices=["fp32", "fp64"], default="fp32")
     ap.add_argument("--n", type=int, default=None, help="override the grid size")
     ap.add_argument("--max-rk-steps", type=int, default=-1,
                     help="stop each solve after this many RK steps (profiling runs only; not a bench value)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the oracle sample")
+    ap.add_argument("--cpu-workers", type=int, default=None,
+                    help="oracle processes of the all-core baseline (default: the host cores, at most 16)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-error-at-t", action="store_true",
+                    help="skip the double-bulk GPU solve that gives the float error at T (2D workloads)")
+    ap.add_argument("--oracle-sample", default=None, help=argparse.SUPPRESS)  # worker mode of the CPU baseline
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a 256 MiB device copy (reference for HBM byte counters)")
     ap.add_argument("--recon", choices=sorted(RECONS), default=None,
@@ -202,54 +237,146 @@ def bench_single(args, w, prec):
     label = kernel_label(w, prec, shape)
     wall, gpu_s, lat, rk = _time_solves(solver, lambda: solver.write(u0_dev, 0.0), w.T, args.steps, args.warmup,
                                         args.max_rk_steps, stream)
+    u_T = solver.read()  # the state at T of the last timed solve (float error at T below)
     ncell = w.ncell
     cell_stages = float(ncell) * 3.0 * rk * args.steps
     esize = 4 if prec == B.FP32 else 8
     launches = 3 * rk * args.steps
     avg_launch = gpu_s / launches
-    bytes_per_launch = ACCESSES_PER_CELL_STAGE * esize * w.ncomp * ncell
-    achieved = bytes_per_launch / avg_launch / 1e9
     out = {
         "value": cell_stages / wall,
         "ms_per_step": 1e3 * wall / args.steps,
         "latency_s": _percentiles(lat),
         "rk_steps_per_solve": rk,
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": counter_traffic(label),
-                     "valu_issue_utilisation": counter_valu(label),
-                     "kernel": label, "avg_launch_us": avg_launch * 1e6,
-                     "bytes_per_launch": bytes_per_launch},
+        "roofline": roofline(w, label, ncell, esize, avg_launch),
         "launch_shape": shape,
+        "u_T": u_T,
     }
     return out, solver, u0_dev
 
 
+def roofline(w, label, cells_per_launch, esize, avg_launch, traffic=None):
+    """Roofline of the dominant kernel (the fused RK stage) from its event-timed average launch.
+    2D and Euler stages are bound by VALU arithmetic (their issue utilisation is at the chip's
+    limit), so they report an ALU roofline with the HBM fraction beside it; the 1D scalar stages
+    report HBM (they are latency-bound, far below either roof)."""
+    bytes_per_launch = ACCESSES_PER_CELL_STAGE * esize * w.ncomp * cells_per_launch
+    gbs = bytes_per_launch / avg_launch / 1e9
+    flops = alg_flops_per_cell_stage(w) * cells_per_launch
+    tflops = flops / avg_launch / 1e12
+    if traffic is None:
+        traffic = counter_traffic(label)
+    hbm = {"achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
+           "bytes_per_launch": bytes_per_launch}
+    alu = {"achieved": tflops, "peak": ALU_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": tflops / ALU_PEAK_TFLOPS,
+           "flops_per_launch": flops, "flops_per_cell_stage": alg_flops_per_cell_stage(w)}
+    common = {"traffic": traffic, "valu_issue_utilisation": counter_valu(label), "kernel": label,
+              "avg_launch_us": avg_launch * 1e6}
+    if w.dim == 2 or w.flux == 2:
+        return {"bound": "alu", **{k: alu[k] for k in ("achieved", "peak", "unit", "frac")}, **common,
+                "flops_per_launch": flops, "peak_basis": "FP32 vector FMA without packed-FP32 instructions",
+                "hbm": hbm}
+    return {"bound": "hbm", **{k: hbm[k] for k in ("achieved", "peak", "unit", "frac")}, **common,
+            "bytes_per_launch": bytes_per_launch, "alu": alu}
+
+
+def oracle_problem(w):
+    import oracle as O
+    return O.Problem(nx=w.nx, ny=w.ny, dim=w.dim, flux=w.flux, ncomp=w.ncomp, bc=w.bc, x0=w.x0, x1=w.x1,
+                     y0=w.y0, y1=w.y1, speed_x=w.speed_x, speed_y=w.speed_y, gamma=w.gamma, cfl=w.cfl,
+                     eps_weno=w.eps_weno, eps_m=w.eps_m, recon=w.recon, switch_mode=w.switch_mode,
+                     charwise=1 if w.variables == 1 else 0)
+
+
+def oracle_initial(w, fp32: bool):
+    return np.asarray(w.u0, np.float32 if fp32 else np.float64).astype(np.float64)
+
+
+def oracle_worker(args):
+    """Worker of the all-core CPU baseline (a child process that never touches the GPU): the first
+    k RK steps of the workload by the FP64 oracle, timed around the oracle call only."""
+    import oracle as O
+    k = int(args.oracle_sample)
+    w, _ = build_workload(args)
+    pb = oracle_problem(w)
+    u = oracle_initial(w, args.precision == "fp32")
+    a = time.perf_counter()
+    _, _, no = O.solve(pb, u, w.T, max_steps=k)
+    el = time.perf_counter() - a
+    print(json.dumps({"seconds": el, "steps": no, "cell_updates": w.ncell * 3.0 * no}), flush=True)
+
+
+def oracle_all_cores(args, k):
+    """k oracle steps in P concurrent child processes (one per host core, at most 16): the host's
+    aggregate oracle throughput on this workload.  The oracle is single-threaded C; the processes
+    run the same sample independently."""
+    import subprocess
+    P = args.cpu_workers or max(1, min(16, len(os.sched_getaffinity(0))))
+    cmd = [sys.executable, os.path.abspath(__file__), "--workload", args.workload, "--precision", args.precision,
+           "--variables", args.variables, "--oracle-sample", str(k)]
+    if args.n is not None:
+        cmd += ["--n", str(args.n)]
+    if args.recon is not None:
+        cmd += ["--recon", args.recon]
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    procs = [subprocess.Popen(cmd, stdout=subprocess.PIPE, text=True, env=env) for _ in range(P)]
+    res = []
+    for p in procs:
+        out, _ = p.communicate()
+        if p.returncode != 0:
+            raise RuntimeError(f"oracle worker failed with status {p.returncode}")
+        res.append(json.loads(out.strip().splitlines()[-1]))
+    rate = sum(r["cell_updates"] / r["seconds"] for r in res)
+    return {"value": rate, "cores": P, "worker_seconds": [float(f"{r['seconds']:.6g}") for r in res]}
+
+
 def cpu_baseline(args, w, solver, u0_dev, prec):
-    """The FP64 oracle on the host, one thread, on a bounded sample of the same solve."""
+    """The FP64 oracle on the host on a bounded sample of the same solve (its first k RK steps):
+    once on one thread in this process, then in one process per host core.  Also the error of the
+    GPU's state after the same k steps against the oracle's."""
     import oracle as O
 
     from paper_1602_00182_amd import binding as B
-    pb = O.Problem(nx=w.nx, ny=w.ny, dim=w.dim, flux=w.flux, ncomp=w.ncomp, bc=w.bc, x0=w.x0, x1=w.x1,
-                   y0=w.y0, y1=w.y1, speed_x=w.speed_x, speed_y=w.speed_y, gamma=w.gamma, cfl=w.cfl,
-                   eps_weno=w.eps_weno, eps_m=w.eps_m, recon=w.recon, switch_mode=w.switch_mode,
-                   charwise=1 if w.variables == 1 else 0)
-    u_ref = np.asarray(w.u0, np.float32 if prec == B.FP32 else np.float64).astype(np.float64)
+    pb = oracle_problem(w)
+    u_ref = oracle_initial(w, prec == B.FP32)
     a = time.perf_counter()
     u1, t1, _ = O.step(pb, u_ref, w.T)
     per_step = time.perf_counter() - a
-    k = max(1, int(args.cpu_seconds / max(per_step, 1e-6)))
+    k = max(2, int(args.cpu_seconds / max(per_step, 1e-6)))
     a = time.perf_counter()
     uo, _, no = O.solve(pb, u1, w.T, t=t1, max_steps=k - 1)
     el = time.perf_counter() - a + per_step
     ksteps = no + 1
-    base = {"value": w.ncell * 3.0 * ksteps / el, "unit": "cell-updates/s", "cores": 1, "kind": "oracle",
-            "sample": f"first {ksteps} RK3 steps of the same solve ({w.name}), FP64, one thread"}
+    one = w.ncell * 3.0 * ksteps / el
+    allc = oracle_all_cores(args, ksteps)
+    base = {"value": allc["value"], "unit": "cell-updates/s", "cores": allc["cores"], "kind": "oracle",
+            "sample": f"first {ksteps} RK3 steps of the same solve ({w.name}), FP64; {allc['cores']} oracle "
+                      f"processes at once, one per host core, each running the whole sample",
+            "single_thread": {"value": one, "cores": 1}, "worker_seconds": allc["worker_seconds"],
+            "host": host_description()}
     solver.write(u0_dev, 0.0)
     solver.solve(w.T, ksteps)
     ug = solver.read().astype(np.float64)
     err = {"vs": "FP64 oracle", "rk_steps": ksteps, "l1": float(np.mean(np.abs(ug - uo))),
            "linf": float(np.max(np.abs(ug - uo)))}
     return base, err
+
+
+def error_at_T(w, u_T, prec):
+    """Float-bulk state at T against the double-bulk GPU path at T (which the parity tests hold
+    bit-identical to the FP64 oracle): L1 and Linf over every cell and component."""
+    import torch
+
+    from paper_1602_00182_amd import binding as B
+    if prec != B.FP32:
+        return None
+    u0 = torch.tensor(w.u0, dtype=torch.float64, device="cuda")
+    with B.Solver(u0, **B.workload_params(w, B.FP64)) as s:
+        st = s.solve(w.T)
+        ref = s.read()
+    d = np.abs(np.asarray(u_T, np.float64) - ref)
+    return {"vs": "double-bulk GPU path at T (bit-identical to the FP64 oracle in the parity tests)",
+            "t": st["t"], "rk_steps": st["nsteps"], "l1": float(d.mean()), "linf": float(d.max())}
 
 
 def cpu_baseline_batch(args, ws, bt, prec):
@@ -351,15 +478,21 @@ def bench_batch(args, prec):
         cb, err = cpu_baseline_batch(args, ws, bt, prec)
     shape = bt.launch_shape()
     bt.close()
+    label = kernel_label(ws[0], prec, shape, batched=True)
+    tflops = alg_flops_per_cell_stage(ws[0]) * total_cell_stages / gpu_s / 1e12
     return {"value": total_cell_stages / wall, "ms_per_step": 1e3 * wall / args.steps,
             "cpu_baseline": cb, "error_vs_oracle": err, "scheme": scheme_of(ws[0]),
             "latency_s": _percentiles(lat), "instances": len(ws), "cells": int(sum(w.nx for w in ws)),
             "max_rk_steps": max_steps,
-            "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                         "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                         "valu_issue_utilisation": counter_valu(kernel_label(ws[0], prec, shape, batched=True)),
-                         "kernel": kernel_label(ws[0], prec, shape, batched=True),
-                         "note": "bytes of all instances / GPU time of the timed region"}}
+            "roofline": {"bound": "alu", "achieved": tflops, "peak": ALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+                         "frac": tflops / ALU_PEAK_TFLOPS, "traffic": counter_traffic(label),
+                         "traffic_note": "HBM bytes per launch while every instance is running (counters over "
+                                         "the first 20 steps)",
+                         "valu_issue_utilisation": counter_valu(label), "kernel": label,
+                         "peak_basis": "FP32 vector FMA without packed-FP32 instructions",
+                         "hbm": {"achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                 "frac": achieved / HBM_PEAK_GBS},
+                         "note": "work of all instances / GPU time of the timed region"}}
 
 
 def bench_serving(args, prec):
@@ -412,10 +545,36 @@ def bench_serving(args, prec):
             "trace": f"first {nreq} requests of the seed-4 Poisson trace, N log-uniform in [256, {args.serving_nmax}]"}
 
 
+def build_workload(args):
+    """The single-grid workload named on the command line and its description."""
+    from paper_1602_00182_amd import inputs as I
+    if args.workload == "advection":
+        w = apply_scheme(args, I.advection_sine(n=args.n or 65536, T=0.5))
+        desc = (f"1D linear advection N={w.nx} periodic, u0 = sin(pi x) (Table 5's problem at the headline's "
+                f"size), {scheme_of(w)}, global LF, SSP-RK3 CFL 0.5 to T=0.5")
+    elif args.workload == "advection2d":
+        w = apply_scheme(args, I.advection2d_sine(n=args.n or 2048))
+        desc = (f"2D linear advection v_t + v_x + v_y = 0 on {w.nx}^2 cells of [0,1]^2, periodic, "
+                f"v0 = sin(2 pi (x + y)) (Section 6's problem), {scheme_of(w)}, CFL 0.4 to T=0.25")
+    elif args.workload == "burgers":
+        w = apply_scheme(args, I.burgers_noisy(n=args.n or 65536, seed=2))
+        desc = (f"1D Burgers N={w.nx} periodic, u0 = 0.5 + sin(pi x) + seeded noise 1e-3, {scheme_of(w)}, "
+                "global LF, SSP-RK3 CFL 0.5 to T=1.5/pi")
+    else:
+        w = apply_scheme(args, I.euler2d_quadrants(n=args.n or 2048))
+        desc = (f"2D Euler {w.nx}^2 on [0,1]^2, four seeded constant quadrant states (rho, p in [0.1,1.5], "
+                f"u, v in [-1,1]) split at (0.5,0.5), transmissive, gamma 1.4, {scheme_of(w)}, dimension by "
+                "dimension with one midpoint point per face, global LF, SSP-RK3 CFL 0.4 to T=0.25")
+    return w, desc
+
+
 def main():
     args = parse()
+    if args.oracle_sample is not None:
+        oracle_worker(args)
+        return
     if args.steps is None:
-        args.steps = {"burgers": 20, "advection": 20, "euler_batch": 2, "euler2d": 1, "advection2d": 3}.get(
+        args.steps = {"burgers": 20, "advection": 20, "euler_batch": 2, "euler2d": 3, "advection2d": 3}.get(
             args.workload, 1)
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -433,22 +592,7 @@ def main():
             "data": "synthetic (seeded)"}
 
     if args.workload in ("burgers", "advection", "euler2d", "advection2d"):
-        if args.workload == "advection":
-            w = apply_scheme(args, I.advection_sine(n=args.n or 65536, T=0.5))
-            desc = (f"1D linear advection N={w.nx} periodic, u0 = sin(pi x) (Table 5's problem at the headline's "
-                    f"size), {scheme_of(w)}, global LF, SSP-RK3 CFL 0.5 to T=0.5")
-        elif args.workload == "advection2d":
-            w = apply_scheme(args, I.advection2d_sine(n=args.n or 2048))
-            desc = (f"2D linear advection v_t + v_x + v_y = 0 on {w.nx}^2 cells of [0,1]^2, periodic, "
-                    f"v0 = sin(2 pi (x + y)) (Section 6's problem), {scheme_of(w)}, CFL 0.4 to T=0.25")
-        elif args.workload == "burgers":
-            w = apply_scheme(args, I.burgers_noisy(n=args.n or 65536, seed=2))
-            desc = (f"1D Burgers N={w.nx} periodic, u0 = 0.5 + sin(pi x) + seeded noise 1e-3, {scheme_of(w)}, "
-                    "global LF, SSP-RK3 CFL 0.5 to T=1.5/pi")
-        else:
-            w = apply_scheme(args, I.euler2d_quadrants(n=args.n or 2048))
-            desc = (f"2D Euler {w.nx}^2 four-quadrant Riemann data, {scheme_of(w)}, dimension by dimension, "
-                    "CFL 0.4 to T=0.25")
+        w, desc = build_workload(args)
         res, solver, u0_dev = bench_single(args, w, prec)
         out = {"metric": METRIC, "value": res["value"], **base, "ms_per_step": res["ms_per_step"],
                "config": {"workload": w.name, "description": desc, "scheme": scheme_of(w), "cells": w.ncell,
@@ -458,6 +602,8 @@ def main():
                "latency_s": res["latency_s"], "roofline": res["roofline"]}
         if args.max_rk_steps >= 0:
             out["note"] = "profiling run: solves stopped after --max-rk-steps; not a benchmark value"
+        if not args.no_error_at_t and args.max_rk_steps < 0:
+            out["error_at_T"] = error_at_T(w, res["u_T"], prec)
         if not args.no_cpu_baseline:
             cb, err = cpu_baseline(args, w, solver, u0_dev, prec)
             out["cpu_baseline"] = cb

@@ -70,3 +70,40 @@ def test_counter_valu_requires_matching_kernel_and_source(tmp_path, monkeypatch)
     monkeypatch.setattr(bench, "kernel_source_hash", lambda: h)
     assert bench.counter_valu("stage2d_kernel<float, Euler, 4, 64, 8, recompute>") == pytest.approx(0.896)
     assert bench.counter_valu("stage2d_kernel<float, Euler, 4, 62, 8, recompute>") is None
+
+
+def test_oracle_worker_and_all_core_baseline():
+    """The all-core CPU baseline runs the oracle sample in child processes (no GPU use): each
+    reports its own time and work, and the aggregate is their summed rate."""
+    import json
+    import types
+
+    import bench
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--workload", "burgers", "--n", "512",
+                        "--oracle-sample", "3"], capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0, r.stderr
+    rec = json.loads(r.stdout.strip().splitlines()[-1])
+    assert rec["steps"] == 3 and rec["cell_updates"] == 512 * 3 * 3 and rec["seconds"] > 0
+    args = types.SimpleNamespace(cpu_workers=2, workload="burgers", precision="fp32", variables="componentwise",
+                                 n=512, recon=None)
+    res = bench.oracle_all_cores(args, 3)
+    assert res["cores"] == 2 and len(res["worker_seconds"]) == 2
+    assert res["value"] == pytest.approx(sum(512 * 9 / t for t in res["worker_seconds"]), rel=1e-2)
+
+
+def test_roofline_bound_per_workload():
+    """2D and Euler stages report the ALU roofline (with the HBM fraction beside it); 1D scalar
+    stages report HBM.  Achieved = algorithmic work per launch / average launch time."""
+    import bench
+    from paper_1602_00182_amd import inputs as I
+    w2 = I.euler2d_quadrants(n=64)
+    r = bench.roofline(w2, "k", w2.ncell, 4, 1e-4, traffic=None)
+    assert r["bound"] == "alu" and r["unit"] == "TFLOP/s"
+    assert bench.alg_flops_per_cell_stage(w2) == 2 * (4 * 130 + 30)
+    assert r["achieved"] == pytest.approx(1100 * 64 * 64 / 1e-4 / 1e12)
+    assert r["frac"] == pytest.approx(r["achieved"] / r["peak"]) and r["peak"] == pytest.approx(78.6432)
+    assert r["hbm"]["achieved"] == pytest.approx(8 / 3 * 4 * 4 * 64 * 64 / 1e-4 / 1e9)
+    w1 = I.burgers_noisy(n=4096)
+    r1 = bench.roofline(w1, "k", w1.ncell, 4, 2e-6, traffic=5.0)
+    assert r1["bound"] == "hbm" and r1["unit"] == "GB/s" and r1["traffic"] == 5.0
+    assert r1["achieved"] == pytest.approx(8 / 3 * 4 * 4096 / 2e-6 / 1e9)
