@@ -53,7 +53,8 @@ enum {
   NPW_ENONFINITE = -4,   /* a cell average became NaN/Inf; state and t stay at the last good step */
   NPW_ENONPHYSICAL = -5, /* Euler density or pressure <= 0; state and t stay at the last good step */
   NPW_EBUSY = -6,        /* serving: request not finished yet */
-  NPW_ENOTFOUND = -7     /* serving: unknown request id */
+  NPW_ENOTFOUND = -7,    /* serving: unknown request id */
+  NPW_ESCRATCH = -8      /* npweno_rhs_noalloc: the grid needs more scratch than its fixed array */
 };
 
 enum { NPW_ADVECTION = 0, NPW_BURGERS = 1, NPW_EULER = 2 };  /* flux type */
@@ -142,6 +143,28 @@ int npweno_solve(npw_solver* s, double t_final, int64_t max_steps, npw_stats* st
  * of eq. (PDE1) for the current state, with alpha of the current state; written to L_out in
  * the state layout (device pointer if out_on_device).  Synchronizes the stream. */
 int npweno_rhs(npw_solver* s, void* L_out, int out_on_device);
+
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): npweno_rhs for a state the caller holds, with no
+ * solver and no allocation.  Writes L(u) of eq. (PDE1) (1D) or eq. (2DIntegral) (2D), with the
+ * Lax-Friedrichs alpha of u, to L_out.  It only enqueues kernels on hip_stream (NULL = the
+ * default stream) and returns without waiting; it calls no hipMalloc, hipFree or memcpy.
+ *   p           as for npweno_create (one grid, 1D or 2D; cfl and dt_fixed are not used).
+ *   u           device pointer, the state in the layout of npweno_create (element type from
+ *               p->precision); read only.
+ *   L_out       device pointer, same layout and size; must not overlap u.
+ *   status_dev  optional device pointer to one int32: receives NPW_OK, or NPW_ENONFINITE /
+ *               NPW_ENONPHYSICAL when u fails the state check (then L_out is left unchanged).
+ * Launch shape: NPW_BLOCK (1D, default 256) or NPW_TILE2D (2D, default 4 = 62 x 8 cells); the
+ * results equal npweno_rhs's with the same shape.
+ * Scratch: the instance record, the spread alpha entries and the state check's partial records
+ * live in one fixed device array of the library (78 336 bytes, one copy per GPU, held until the
+ * process ends).  Every grid within npweno_create's limits fits; a grid that would not returns
+ * NPW_ESCRATCH.  All calls on one GPU share that array: calls that overlap on one GPU (different
+ * streams or host threads) race, so a caller orders them on one stream.
+ * Returns NPW_EINVAL for a bad parameter, a NULL pointer or overlapping buffers, NPW_EHIP if a
+ * launch fails; errors of the state itself arrive through status_dev. */
+int npweno_rhs_noalloc(const npw_params* p, const void* u, void* L_out, void* hip_stream, int32_t* status_dev);
 
 /* Copy the current state out (device pointer if out_on_device).  Synchronizes the stream. */
 int npweno_read(const npw_solver* s, void* u_out, int out_on_device);

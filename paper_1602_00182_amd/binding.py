@@ -15,7 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libnpweno.so")
 
 NPW_ABI_VERSION = 2
-OK, EINVAL, ENOMEM, EHIP, ENONFINITE, ENONPHYSICAL, EBUSY, ENOTFOUND = 0, -1, -2, -3, -4, -5, -6, -7
+OK, EINVAL, ENOMEM, EHIP, ENONFINITE, ENONPHYSICAL, EBUSY, ENOTFOUND, ESCRATCH = 0, -1, -2, -3, -4, -5, -6, -7, -8
 ADVECTION, BURGERS, EULER = 0, 1, 2
 PERIODIC, TRANSMISSIVE = 0, 1
 FP64, FP32 = 0, 1
@@ -84,6 +84,7 @@ def lib():
         L.npweno_solve.argtypes = [_VP, ctypes.c_double, ctypes.c_int64, S]
         L.npweno_rhs.argtypes = [_VP, _VP, ctypes.c_int]
         L.npweno_read.argtypes = [_VP, _VP, ctypes.c_int]
+        L.npweno_rhs_noalloc.argtypes = [P, _VP, _VP, _VP, _VP]
         L.npweno_write.argtypes = [_VP, _VP, ctypes.c_int, ctypes.c_double]
         L.npweno_get_stats.argtypes = [_VP, S]
         L.npweno_destroy.argtypes = [_VP]
@@ -111,7 +112,7 @@ def lib():
         for name in ("npw_server_create", "npw_server_submit", "npw_server_pump", "npw_server_poll",
                      "npw_server_times", "npw_server_release"):
             getattr(L, name).restype = ctypes.c_int
-        for name in ("npweno_create", "npweno_step", "npweno_solve", "npweno_rhs", "npweno_read",
+        for name in ("npweno_create", "npweno_step", "npweno_solve", "npweno_rhs", "npweno_rhs_noalloc", "npweno_read",
                      "npweno_write", "npweno_get_stats", "npweno_create_batch", "npweno_solve_batch",
                      "npweno_read_instance", "npweno_get_stats_instance"):
             getattr(L, name).restype = ctypes.c_int
@@ -162,6 +163,28 @@ def _buf(x, dtype):
         return ctypes.c_void_p(x.data_ptr()), 1, x
     a = np.ascontiguousarray(x, dtype=dtype)
     return a.ctypes.data_as(ctypes.c_void_p), 0, a
+
+
+def rhs_noalloc(u, L_out, status=None, stream=None, **params):
+    """npweno_rhs_noalloc: L(u) of a caller-held device state into L_out (torch CUDA tensors of the
+    precision's dtype), enqueued on the stream without allocating; `status` (optional int32 CUDA
+    tensor of one element) receives the state check's code.  Returns without synchronizing."""
+    p = make_params(**params)
+    dtype = np.float64 if p.precision == FP64 else np.float32
+    up, udev, _ = _buf(u, dtype)
+    lp, ldev, _ = _buf(L_out, dtype)
+    if not (udev and ldev):
+        raise TypeError("rhs_noalloc takes device tensors")
+    n = int(p.ncomp * p.nx * (p.ny if p.dim == 2 else 1))
+    if u.numel() != n or L_out.numel() != n:
+        raise ValueError(f"u and L_out must hold {n} elements")
+    sp = _VP(0)
+    if status is not None:
+        import torch
+        if status.dtype != torch.int32 or not status.is_cuda or status.numel() != 1:
+            raise TypeError("status must be a one-element int32 CUDA tensor")
+        sp = _VP(status.data_ptr())
+    _check(lib().npweno_rhs_noalloc(ctypes.byref(p), up, lp, _stream_handle(stream), sp), "npweno_rhs_noalloc")
 
 
 class Solver:

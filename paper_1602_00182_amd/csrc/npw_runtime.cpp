@@ -11,6 +11,7 @@
 #include <cstring>
 #include <fstream>
 #include <map>
+#include <mutex>
 #include <sstream>
 #include <string>
 #include <new>
@@ -578,6 +579,7 @@ const char* npweno_strerror(int code) {
     case NPW_ENONPHYSICAL: return "non-physical Euler state (density or pressure <= 0)";
     case NPW_EBUSY: return "request not finished";
     case NPW_ENOTFOUND: return "unknown request";
+    case NPW_ESCRATCH: return "the grid needs more scratch than the fixed device array holds";
     default: return "unknown error";
   }
 }
@@ -947,6 +949,126 @@ static void npweno_destroy_impl(npw_solver* s) {
 
 }  // extern "C"
 
+// ---- The allocation-free right-hand side ---------------------------------------------------
+// Its scratch lives in one fixed device array of this translation unit, one copy per GPU:
+//   [0, 512)                 the instance record (InstDev)
+//   [512, 512 + 49152)       the spread alpha entries of a single grid (kSpreadWords words)
+//   [49664, 49664 + 28672)   the state check's partial records (kCheckMaxG records)
+// Every grid within the limits of npweno_create fits, since the check uses at most kCheckMaxG
+// workgroups.  Host code reaches the array only through the address hipGetSymbolAddress gives
+// for the current device (the array's name in host code is a stand-in, not a device address).
+namespace {
+constexpr size_t kNaRecordBytes = 512;
+constexpr size_t kNaSpreadBytes = sizeof(unsigned long long) * npw::kSpreadWords;
+constexpr int kCheckMaxG = 512;
+constexpr size_t kNaPartialBytes = (size_t)npw::kCheckPartialBytes * kCheckMaxG;
+constexpr size_t kNoAllocScratchBytes = kNaRecordBytes + kNaSpreadBytes + kNaPartialBytes;
+static_assert(sizeof(InstDev) <= kNaRecordBytes, "the instance record fits its slot");
+static_assert(kNoAllocScratchBytes <= 80 * 1024, "the scratch array stays modest");
+static_assert(kNaSpreadBytes % 256 == 0, "the partial records start 256-byte aligned");
+constexpr int kMaxDevices = 64;
+
+std::mutex g_scratch_mutex;
+void* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+namespace {
+// Device address of `scratch` on the current device, looked up once per device.
+int scratch_address(void** out) {
+  int dev = -1;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return NPW_EINVAL;
+  std::lock_guard<std::mutex> lock(g_scratch_mutex);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return NPW_EHIP;
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return NPW_OK;
+}
+
+// Write the instance record (static part from the parameters, dynamic part zero: t = 0, step 0,
+// no error, alpha slots clear) without a host copy, so nothing reads host memory after return.
+__global__ void noalloc_record_kernel(InstDev* rec, InstDev v) {
+  const unsigned* src = reinterpret_cast<const unsigned*>(&v);
+  unsigned* dst = reinterpret_cast<unsigned*>(rec);
+  for (int k = threadIdx.x; k < (int)(sizeof(InstDev) / sizeof(unsigned)); k += blockDim.x) dst[k] = src[k];
+}
+
+// Copy the state check's verdict (NPW_OK, NPW_ENONFINITE or NPW_ENONPHYSICAL) to the caller.
+__global__ void noalloc_status_kernel(const InstDev* rec, int32_t* status) { *status = rec->err; }
+
+int rhs_noalloc_impl(const npw_params* p, const void* u, void* L_out, void* hip_stream, int32_t* status_dev) {
+  if (!p || !u || !L_out) return NPW_EINVAL;
+  int rc = validate(p);
+  if (rc) return rc;
+  const long long ny = p->dim == 2 ? p->ny : 1;
+  const size_t esize = p->precision == NPW_FP64 ? sizeof(double) : sizeof(float);
+  const size_t bytes = (size_t)p->ncomp * (size_t)(p->nx * ny) * esize;
+  const char* ub = static_cast<const char*>(u);
+  const char* lb = static_cast<const char*>(L_out);
+  if (ub < lb + bytes && lb < ub + bytes) return NPW_EINVAL;  // L_out must not overlap u
+  const long long cells = p->nx * ny;
+  const int G = (int)std::min<long long>(kCheckMaxG, std::max<long long>(1, cells / 16384));
+  if (kNaRecordBytes + kNaSpreadBytes + (size_t)npw::kCheckPartialBytes * G > kNoAllocScratchBytes)
+    return NPW_ESCRATCH;
+  void* base = nullptr;
+  rc = scratch_address(&base);
+  if (rc) return rc;
+  char* sc = static_cast<char*>(base);
+  InstDev* rec = reinterpret_cast<InstDev*>(sc);
+  unsigned long long* spread = reinterpret_cast<unsigned long long*>(sc + kNaRecordBytes);
+  void* part = sc + kNaRecordBytes + kNaSpreadBytes;
+  hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+
+  noalloc_record_kernel<<<1, 64, 0, st>>>(rec, make_inst(p, 0));
+  HIP_TRY(hipGetLastError());
+  void* uu = const_cast<void*>(u);  // read only: rhs mode loads the state and writes L_out
+  const int flux = p->flux, m = p->ncomp;
+  HIP_TRY(p->precision == NPW_FP64 ? npw::launch_init_f64(flux, m, rec, 1, uu, uu, spread, part, G, st)
+                                   : npw::launch_init_f32(flux, m, rec, 1, uu, uu, spread, part, G, st));
+  StageArgs a;
+  std::memset(&a, 0, sizeof a);
+  a.inst = rec;
+  a.tiles = nullptr;
+  a.nx = p->nx;
+  a.ny = ny;
+  a.bc = p->bc;
+  a.par = 0;
+  a.P0 = uu;
+  a.P1 = uu;
+  a.C = uu;
+  a.out = L_out;
+  a.stage = 0;
+  a.charw = p->variables == NPW_CHARACTERISTIC ? 1 : 0;
+  a.any_k2 = p->recon >= NPW_RBF_WENO3 ? 1 : 0;
+  a.spread = spread;
+  if (p->dim == 1) {
+    const int block = env_block();
+    a.ntiles = (int)((p->nx + block - 3) / (block - 2));
+    HIP_TRY(p->precision == NPW_FP64 ? npw::launch_stage_f64(flux, m, block, a, st)
+                                     : npw::launch_stage_f32(flux, m, block, a, st));
+  } else {
+    int shape = 4;  // 62 x 8 cells, per-interface recompute
+    if (const char* e = std::getenv("NPW_TILE2D")) {
+      const int v = std::atoi(e);
+      if (v >= 0 && v < npw::k2dShapes) shape = v;
+    }
+    HIP_TRY(p->precision == NPW_FP64 ? npw::launch_stage2d_f64(flux, m, shape, a, st)
+                                     : npw::launch_stage2d_f32(flux, m, shape, a, st));
+  }
+  if (status_dev) {
+    noalloc_status_kernel<<<1, 1, 0, st>>>(rec, status_dev);
+    HIP_TRY(hipGetLastError());
+  }
+  return NPW_OK;
+}
+}  // namespace
+
 // ---- C ABI entry points: no C++ exception crosses the boundary ------------------------
 // (std containers may throw std::bad_alloc; every entry point maps that to NPW_ENOMEM.)
 template <typename F>
@@ -1011,6 +1133,10 @@ int npweno_rhs(npw_solver* s, void* L_out, int out_on_device) {
 
 int npweno_read(const npw_solver* cs, void* u_out, int out_on_device) {
   return guarded([&] { return npweno_read_impl(cs, u_out, out_on_device); });
+}
+
+int npweno_rhs_noalloc(const npw_params* p, const void* u, void* L_out, void* hip_stream, int32_t* status_dev) {
+  return guarded([&] { return rhs_noalloc_impl(p, u, L_out, hip_stream, status_dev); });
 }
 
 int npweno_get_stats(const npw_solver* cs, npw_stats* stats) {

@@ -79,3 +79,21 @@ def test_null_arguments_rejected(L):
     assert L.npweno_solve(None, 1.0, -1, None) == B.EINVAL
     assert L.npweno_read(None, None, 0) == B.EINVAL
     L.npweno_destroy(None)
+
+
+def test_rhs_noalloc_rejects_bad_arguments_before_touching_the_gpu(L):
+    """npweno_rhs_noalloc validates parameters, NULL pointers and overlapping buffers before any
+    HIP call (the pointers here are never dereferenced)."""
+    from paper_1602_00182_amd import binding as B
+    ok = B.make_params(nx=80)
+    u, out = ctypes.c_void_p(1 << 20), ctypes.c_void_p(1 << 24)
+    assert L.npweno_rhs_noalloc(None, u, out, None, None) == B.EINVAL
+    assert L.npweno_rhs_noalloc(ctypes.byref(ok), None, out, None, None) == B.EINVAL
+    assert L.npweno_rhs_noalloc(ctypes.byref(ok), u, None, None, None) == B.EINVAL
+    for bad in ({"nx": 0}, {"flux": 2, "ncomp": 1}, {"recon": 8}, {"reserved": 1}):
+        p = B.make_params(**bad)
+        assert L.npweno_rhs_noalloc(ctypes.byref(p), u, out, None, None) == B.EINVAL
+    # L_out overlapping u (80 doubles = 640 bytes): rejected; adjacent is fine (not called here)
+    assert L.npweno_rhs_noalloc(ctypes.byref(ok), u, ctypes.c_void_p((1 << 20) + 632), None, None) == B.EINVAL
+    assert L.npweno_rhs_noalloc(ctypes.byref(ok), ctypes.c_void_p((1 << 20) + 8), u, None, None) == B.EINVAL
+    assert len(L.npweno_strerror(B.ESCRATCH)) > 0
