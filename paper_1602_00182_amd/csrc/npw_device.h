@@ -29,13 +29,21 @@ __device__ __forceinline__ int ghost_index(int k, int n, int bc) {
 // Faithful double quotient (error below one unit in the last place) for normal operands: the
 // hardware reciprocal, one Newton step (relative error about the square of the reciprocal's) and
 // one residual correction.  (Checked against the correctly rounded quotient on 4 million operand
-// pairs spanning 1e-12..1e6: all equal.)  Used by the float bulk path for double ratios that are
-// rounded to float afterwards, and as the first step of div_rn.
+// pairs spanning 1e-12..1e6: all equal.)  The first step of div_rn.
 __device__ __forceinline__ double div_faithful(double a, double b) {
   double r = __builtin_amdgcn_rcp(b);
   r = fma(fma(-b, r, 1.0), r, r);
   const double q = a * r;
   return fma(fma(-b, q, a), r, q);
+}
+
+// Double quotient from the hardware reciprocal refined by one Newton step (relative error about
+// the square of the reciprocal's, a couple of units in the last place of double).  The float bulk
+// forms its double shape parameter with it and rounds the result to float.
+__device__ __forceinline__ double div_newton(double a, double b) {
+  double r = __builtin_amdgcn_rcp(b);
+  r = fma(fma(-b, r, 1.0), r, r);
+  return a * r;
 }
 
 // Correctly rounded double division (round to nearest, ties to even).  The instruction sequence
@@ -58,6 +66,37 @@ __device__ __forceinline__ double div_rn(double a, double b) {
   const double q1 = __longlong_as_double(nb);
   const double e0 = fabs(r), e1 = fabs(fma(-q1, b, a));
   return (e1 < e0 || (e1 == e0 && (nb & 1) == 0)) ? q1 : q;
+}
+
+// Raw buffer access: a resource over n_bytes from base, addressed by a 32-bit lane offset plus a
+// uniform (scalar) offset, both in bytes, so that each component of a state is reached by changing
+// only the scalar offset.  The hardware checks every access against n_bytes (loads out of range
+// read 0 and such stores are dropped).  Word 3 of the descriptor: 32-bit data format, the value
+// gfx9-family raw buffers take.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_of(const void* base, unsigned n_bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)n_bytes, 0x00020000);
+}
+typedef int npw_int2 __attribute__((ext_vector_type(2)));
+template <typename R>
+__device__ __forceinline__ R buffer_load(__amdgpu_buffer_rsrc_t r, unsigned lane_bytes, unsigned uniform_bytes) {
+  if constexpr (sizeof(R) == 4) {
+    return __int_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, (int)lane_bytes, (int)uniform_bytes, 0));
+  } else {
+    const npw_int2 v = __builtin_amdgcn_raw_buffer_load_b64(r, (int)lane_bytes, (int)uniform_bytes, 0);
+    return __longlong_as_double(((long long)(unsigned)v.y << 32) | (unsigned)v.x);
+  }
+}
+template <typename R>
+__device__ __forceinline__ void buffer_store(R x, __amdgpu_buffer_rsrc_t r, unsigned lane_bytes, unsigned uniform_bytes) {
+  if constexpr (sizeof(R) == 4) {
+    __builtin_amdgcn_raw_buffer_store_b32(__float_as_int(x), r, (int)lane_bytes, (int)uniform_bytes, 0);
+  } else {
+    const long long b = __double_as_longlong(x);
+    npw_int2 v;
+    v.x = (int)(unsigned)b;
+    v.y = (int)(b >> 32);
+    __builtin_amdgcn_raw_buffer_store_b64(v, r, (int)lane_bytes, (int)uniform_bytes, 0);
+  }
 }
 
 // Division and square root in the bulk precision: correctly rounded in double (the exact
@@ -84,13 +123,13 @@ __device__ __forceinline__ R fsqrt(R a) {
 // not monotone when 0 < x_p/dx < 3.  Division by zero (linear data) gives inf/NaN, which fails
 // the strict test.  Double precision, uncontracted: the decision is the one the quotient makes.
 // CR (double bulk): the test on the correctly rounded quotient, as written.  Otherwise (float
-// bulk: the window holds float values, so num and den are exact in double and 3 den is too) the
-// same decision without the quotient: 0 < num/den < 3 holds exactly when num and den are non-zero
-// with one sign and num lies on the near side of 3 den.  A quotient of such operands cannot lie
-// within rounding distance of 0 or 3 without equalling it, so both forms decide alike.
-// In the float bulk the window's doubles are float values, so the differences p = u0 - um1 and
-// q = up1 - u0 and every small-integer combination of them below are exact; num = 2p - q and
-// den = p - q are then the same numbers as the forms written above, in fewer operations.
+// bulk: the window holds float values, so the differences p = u0 - um1 and q = up1 - u0 and the
+// small-integer combinations of them below are exact in double) the same decision without the
+// quotient.  With num = 2p - q and den = p - q, 0 < num/den < 3 holds exactly when num and den are
+// non-zero with one sign and num - 3 den = -(p - 2q) has the opposite sign to den, i.e. when
+// t1 = p - q, t2 = 2p - q and t3 = p - 2q are all non-zero with one sign: t1 t2 > 0 and t1 t3 > 0
+// (products of float differences neither overflow nor underflow in double).  Ties (an extremum
+// exactly at 0 or 3 dx) make t2 or t3 zero and are not flagged, as the strict inequalities say.
 template <bool CR = true>
 __device__ __forceinline__ int monotone_flag(double um1, double u0, double up1) {
 #pragma clang fp contract(off)
@@ -101,16 +140,16 @@ __device__ __forceinline__ int monotone_flag(double um1, double u0, double up1) 
     return (xp > 0.0 && xp < 3.0) ? 1 : 0;
   } else {
     const double p = u0 - um1, q = up1 - u0;
-    const double num = fma(2.0, p, -q), den = p - q;
-    if (num == 0.0 || den == 0.0 || (num > 0.0) != (den > 0.0)) return 0;
-    return (den > 0.0 ? num < 3.0 * den : num > 3.0 * den) ? 1 : 0;
+    const double t1 = p - q, t2 = p + t1, t3 = t1 - q;
+    return (t1 * t2 > 0.0 && t1 * t3 > 0.0) ? 1 : 0;
   }
 }
 
 // Shape parameter eta = eps^2 dx^2 at x_{i+1/2} (Table 3 caption) from u_{i-1}..u_{i+2}:
 // third over (weighted) first undivided difference; eps_M is added with the sign of the
 // denominator so that it never crosses zero.  Double precision, uncontracted.
-// (Float bulk: with s = um1 - up2 and d = up1 - u0, both exact, num = s + 3d and den = s + 15d.)
+// (Float bulk: with s = um1 - up2 and d = up1 - u0, both exact, num = s + 3d and den = s + 15d,
+// and the double quotient of div_newton, which the caller rounds to float.)
 template <bool CR = true>
 __device__ __forceinline__ double eta_ratio(double um1, double u0, double up1, double up2, double eps_m) {
 #pragma clang fp contract(off)
@@ -127,7 +166,7 @@ __device__ __forceinline__ double eta_ratio(double um1, double u0, double up1, d
     den = den + eps_m;
   else
     den = den - eps_m;
-  return CR ? div_rn(num, den) : div_faithful(num, den);
+  return CR ? div_rn(num, den) : div_newton(num, den);
 }
 
 // Jiang-Shu smoothness indicators of cell i from (a..e) = u_{i-2}..u_{i+2}; b0 for the stencil
@@ -343,7 +382,7 @@ __device__ __forceinline__ double eta2_ratio(double ufar, double u0, double unea
     den = den + eps_m;
   else
     den = den - eps_m;
-  return CR ? div_rn(num, den) : div_faithful(num, den);
+  return CR ? div_rn(num, den) : div_newton(num, den);
 }
 
 // WENO3 edge values of cell i from (a, b, c) = u_{i-1}, u_i, u_{i+1}: v^-_{i+1/2} combines row 0 on
@@ -428,7 +467,7 @@ __device__ __forceinline__ R cross_edge(R a, R b, R c, R ts, R tn, bool use_swit
     den = den + eps_m;
   else
     den = den - eps_m;
-  const double eta = kCR ? div_rn(num, den) : div_faithful(num, den);
+  const double eta = kCR ? div_rn(num, den) : div_newton(num, den);
   return P + R(eta) * P;
 }
 
@@ -655,6 +694,39 @@ __device__ __forceinline__ R spectral_radius(const R* U, R speed, R gamma, int& 
       return R(0);
     }
     return fabs(DIR == 0 ? u : v) + fsqrt(fdiv(gamma * p, rho));
+  }
+}
+
+// Spectral radii along x and y at one state (2D), with validity as in spectral_radius: the
+// velocity quotients, the pressure and the sound speed are formed once for both directions (the
+// same operations as spectral_radius, so each radius is the same number).
+template <typename R, int FLUX, int M>
+__device__ __forceinline__ void spectral_radii_2d(const R* U, R speed_x, R speed_y, R gamma, R& sx, R& sy,
+                                                  int& bad) {
+  bad = 0;
+  sx = R(0);
+  sy = R(0);
+#pragma unroll
+  for (int c = 0; c < M; ++c)
+    if (!isfinite(U[c])) bad = 1;
+  if (bad) return;
+  if constexpr (FLUX == kAdvection) {
+    sx = fabs(speed_x);
+    sy = fabs(speed_y);
+  } else if constexpr (FLUX == kBurgers) {
+    sx = fabs(U[0]);
+    sy = sx;
+  } else {
+    static_assert(M == 4, "2D Euler has four components");
+    R rho = U[0], u = fdiv(U[1], rho), v = fdiv(U[2], rho);
+    R p = (gamma - R(1.0)) * (U[3] - R(0.5) * rho * (u * u + v * v));
+    if (!(rho > R(0)) || !(p > R(0))) {
+      bad = 2;
+      return;
+    }
+    const R c = fsqrt(fdiv(gamma * p, rho));
+    sx = fabs(u) + c;
+    sy = fabs(v) + c;
   }
 }
 

@@ -72,15 +72,36 @@ __global__ __launch_bounds__(256) void stage2d_kernel(StageArgs a) {
   R* dst = stage == 0 ? reinterpret_cast<R*>(a.out) : (stage == 2 ? u2 : uo);
 
   // ---- issue the state loads (tile + halo, every component) -------------------------------
+  // Tiles whose halo lies inside the grid (all but the edge tiles) of states below 4 GiB need no
+  // ghost mapping and address through buffer resources: one 32-bit lane offset per cell, the
+  // component in the scalar offset.  The test is uniform over the workgroup.
+  const unsigned state_bytes = (unsigned)((unsigned long long)M * ncell * sizeof(R));
+  const bool direct = i0 >= 3 && i0 + TX + 3 <= nx && j0 >= 3 && j0 + TY + 3 <= ny &&
+                      (unsigned long long)M * ncell * sizeof(R) < (1ULL << 32);
+  const unsigned comp_bytes = (unsigned)(ncell * sizeof(R));  // used only when direct
   constexpr int NLD = (WX * WY + BS - 1) / BS;
   R ld[NLD][M];
+  if (direct) {
+    const __amdgpu_buffer_rsrc_t rs = buffer_of(src, state_bytes);
+    const unsigned corner = (unsigned)(j0 - 3) * (unsigned)nx + (unsigned)(i0 - 3);
 #pragma unroll
-  for (int k = 0; k < NLD; ++k) {
-    const int idx = tid + k * BS;
-    if (idx < WX * WY) {
-      const int gy = ghost_index(j0 - 3 + idx / WX, ny, bc), gx = ghost_index(i0 - 3 + idx % WX, nx, bc);
+    for (int k = 0; k < NLD; ++k) {
+      const int idx = tid + k * BS;
+      if (idx < WX * WY) {
+        const unsigned at = (corner + (unsigned)(idx / WX) * (unsigned)nx + (unsigned)(idx % WX)) * sizeof(R);
 #pragma unroll
-      for (int c = 0; c < M; ++c) ld[k][c] = src[c * ncell + (long long)gy * nx + gx];
+        for (int c = 0; c < M; ++c) ld[k][c] = buffer_load<R>(rs, at, c * comp_bytes);
+      }
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < NLD; ++k) {
+      const int idx = tid + k * BS;
+      if (idx < WX * WY) {
+        const int gy = ghost_index(j0 - 3 + idx / WX, ny, bc), gx = ghost_index(i0 - 3 + idx % WX, nx, bc);
+#pragma unroll
+        for (int c = 0; c < M; ++c) ld[k][c] = src[c * ncell + (long long)gy * nx + gx];
+      }
     }
   }
   constexpr int NOWN = (TX * TY + BS - 1) / BS;
@@ -91,8 +112,15 @@ __global__ __launch_bounds__(256) void stage2d_kernel(StageArgs a) {
       const int o = tid + k * BS;
       const int x = i0 + o % TX, y = j0 + o / TX;
       if (o < TX * TY && x < nx && y < ny) {
+        if (direct) {
+          const __amdgpu_buffer_rsrc_t rs = buffer_of(un, state_bytes);
+          const unsigned at = ((unsigned)y * (unsigned)nx + (unsigned)x) * sizeof(R);
 #pragma unroll
-        for (int c = 0; c < M; ++c) upt[k][c] = un[c * ncell + (long long)y * nx + x];
+          for (int c = 0; c < M; ++c) upt[k][c] = buffer_load<R>(rs, at, c * comp_bytes);
+        } else {
+#pragma unroll
+          for (int c = 0; c < M; ++c) upt[k][c] = un[c * ncell + (long long)y * nx + x];
+        }
       }
     }
   }
@@ -183,7 +211,7 @@ __global__ __launch_bounds__(256) void stage2d_kernel(StageArgs a) {
   const R alpha_x = R(bits_to_double(ax_bits)), alpha_y = R(bits_to_double(ay_bits));
   const R rdt = R(dt);
   ReconMode rm = recon_mode(I->recon, I->sw);
-  if (!K2) rm.k2 = false;  // launched for a k = 3 instance
+  if (!K2) rm.k2 = rm.cross = false;  // launched for a k = 3 instance (Section 6 is k = 2)
   const bool k2 = rm.k2, eno = rm.eno, use_eta = rm.use_eta, use_switch = rm.use_switch, cross = rm.cross;
   const double eps_m = I->eps_m;
   const R eps = R(I->eps_weno);
@@ -522,13 +550,19 @@ __global__ __launch_bounds__(256) void stage2d_kernel(StageArgs a) {
         unew[c] = L;
       else
         unew[c] = rk3_combine<R>(stage, upt[k][c], us, rdt * L);
-      dst[c * ncell + at] = unew[c];
+    }
+    if (direct) {
+      const __amdgpu_buffer_rsrc_t rs = buffer_of(dst, state_bytes);
+#pragma unroll
+      for (int c = 0; c < M; ++c) buffer_store<R>(unew[c], rs, (unsigned)at * sizeof(R), c * comp_bytes);
+    } else {
+#pragma unroll
+      for (int c = 0; c < M; ++c) dst[c * ncell + at] = unew[c];
     }
     if (stage != 0) {
-      int b0 = 0, b1 = 0;
-      R sx = spectral_radius<R, FLUX, M, 0>(unew, speed_x, gamma, b0);
-      R sy = spectral_radius<R, FLUX, M, 1>(unew, speed_y, gamma, b1);
-      if constexpr (FLUX == kAdvection) sy = fabs(speed_y);
+      int b0 = 0;
+      R sx, sy;
+      spectral_radii_2d<R, FLUX, M>(unew, speed_x, speed_y, gamma, sx, sy, b0);
       amx = sx > amx ? sx : amx;
       amy = sy > amy ? sy : amy;
       bad = b0 > bad ? b0 : bad;
