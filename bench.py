@@ -179,6 +179,12 @@ def parse():
     return ap.parse_args()
 
 
+def progress(msg: str) -> None:
+    """One line on stderr per finished piece of work (a solve, a baseline leg), so a long run shows
+    that it is moving; the result stays the single JSON line on stdout."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def _percentiles(x):
     return {"p50": float(np.percentile(x, 50)), "p99": float(np.percentile(x, 99))}
 
@@ -187,15 +193,16 @@ def _time_solves(solver, reset, T, steps, warmup, max_rk, stream):
     """Wall time of `steps` reset+solve rounds, plus the GPU time of the solves alone: a pair of
     events on the solver's stream brackets each solve(), so the state reset is not counted."""
     import torch
-    for _ in range(warmup):
+    for i in range(warmup):
         reset()
         solver.solve(T, max_rk)
+        progress(f"warmup solve {i + 1}/{warmup} done")
     torch.cuda.synchronize()
     lat = []
     evs = []
     t0 = time.perf_counter()
     rk = 0
-    for _ in range(steps):
+    for i in range(steps):
         a = time.perf_counter()
         reset()
         e0 = torch.cuda.Event(enable_timing=True)
@@ -206,6 +213,7 @@ def _time_solves(solver, reset, T, steps, warmup, max_rk, stream):
         evs.append((e0, e1))
         lat.append(time.perf_counter() - a)
         rk = st["nsteps"]
+        progress(f"timed solve {i + 1}/{steps}: {lat[-1]:.3f} s, {rk} RK steps")
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     gpu_s = sum(e0.elapsed_time(e1) for e0, e1 in evs) / 1e3
@@ -234,6 +242,7 @@ def bench_single(args, w, prec):
     stream = torch.cuda.Stream()
     solver = B.Solver(u0_dev, stream=stream.cuda_stream, **B.workload_params(w, prec))
     shape = solver.launch_shape()
+    progress(f"solver created ({w.name}, launch shape {shape})")
     label = kernel_label(w, prec, shape)
     wall, gpu_s, lat, rk = _time_solves(solver, lambda: solver.write(u0_dev, 0.0), w.T, args.steps, args.warmup,
                                         args.max_rk_steps, stream)
@@ -343,12 +352,15 @@ def cpu_baseline(args, w, solver, u0_dev, prec):
     u1, t1, _ = O.step(pb, u_ref, w.T)
     per_step = time.perf_counter() - a
     k = max(2, int(args.cpu_seconds / max(per_step, 1e-6)))
+    progress(f"oracle: first RK step on one thread took {per_step:.2f} s; sample = {k} steps")
     a = time.perf_counter()
     uo, _, no = O.solve(pb, u1, w.T, t=t1, max_steps=k - 1)
     el = time.perf_counter() - a + per_step
     ksteps = no + 1
     one = w.ncell * 3.0 * ksteps / el
+    progress(f"oracle on one thread: {ksteps} steps in {el:.2f} s")
     allc = oracle_all_cores(args, ksteps)
+    progress(f"oracle on {allc['cores']} processes done")
     base = {"value": allc["value"], "unit": "cell-updates/s", "cores": allc["cores"], "kind": "oracle",
             "sample": f"first {ksteps} RK3 steps of the same solve ({w.name}), FP64; {allc['cores']} oracle "
                       f"processes at once, one per host core, each running the whole sample",
@@ -374,6 +386,7 @@ def error_at_T(w, u_T, prec):
     with B.Solver(u0, **B.workload_params(w, B.FP64)) as s:
         st = s.solve(w.T)
         ref = s.read()
+    progress(f"double-bulk reference solve to T done ({st['nsteps']} RK steps)")
     d = np.abs(np.asarray(u_T, np.float64) - ref)
     return {"vs": "double-bulk GPU path at T (bit-identical to the FP64 oracle in the parity tests)",
             "t": st["t"], "rk_steps": st["nsteps"], "l1": float(d.mean()), "linf": float(d.max())}
@@ -448,15 +461,16 @@ def bench_batch(args, prec):
     def reset():
         B.lib().npweno_write(bt.h, B.ctypes.c_void_p(packed_dev.data_ptr()), 1, 0.0)
 
-    for _ in range(args.warmup):
+    for i in range(args.warmup):
         reset()
         bt.solve(T, args.max_rk_steps)
+        progress(f"warmup batch solve {i + 1}/{args.warmup} done")
     torch.cuda.synchronize()
     lat = []
     evs = []
     t0 = time.perf_counter()
     total_cell_stages = 0.0
-    for _ in range(args.steps):
+    for i in range(args.steps):
         a = time.perf_counter()
         reset()
         e0 = torch.cuda.Event(enable_timing=True)
@@ -467,6 +481,7 @@ def bench_batch(args, prec):
         evs.append((e0, e1))
         lat.append(time.perf_counter() - a)
         total_cell_stages += sum(w.nx * 3.0 * s["nsteps"] for w, s in zip(ws, stats))
+        progress(f"timed batch solve {i + 1}/{args.steps}: {lat[-1]:.3f} s")
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     gpu_s = sum(e0.elapsed_time(e1) for e0, e1 in evs) / 1e3
@@ -585,6 +600,7 @@ def main():
     from paper_1602_00182_amd import binding as B
     from paper_1602_00182_amd import inputs as I
     torch.cuda.set_device(0)
+    progress("torch and the library loaded")
     prec = B.FP32 if args.precision == "fp32" else B.FP64
     dname = "f32" if prec == B.FP32 else "f64"
     base = {"unit": "cell-updates/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
