@@ -246,12 +246,11 @@ __device__ __forceinline__ void stage1d_tile(const StageArgs& a, const Tile tile
         }
         continue;
       }
-      double e = 0.0;
+      R eta = R(0);
       if (use_eta) {
-        e = eta_ratio<kExact>(D(c, tid + 1), D(c, tid + 2), D(c, tid + 3), D(c, tid + 4), eps_m);
-        if (use_switch && ((s_flag[c][tid] | s_flag[c][tid + 1]) & 1)) e = 0.0;
+        eta = R(eta_ratio<kExact>(D(c, tid + 1), D(c, tid + 2), D(c, tid + 3), D(c, tid + 4), eps_m));
+        if (use_switch && ((s_flag[c][tid] | s_flag[c][tid + 1]) & 1)) eta = R(0);
       }
-      const R eta = R(e);
       if (eno) {
         A[c] = eno_minus<R>(s_flag[c][tid] >> 1, s_u[c][tid], s_u[c][tid + 1], s_u[c][tid + 2], s_u[c][tid + 3],
                             s_u[c][tid + 4], eta);

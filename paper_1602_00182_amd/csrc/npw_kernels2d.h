@@ -22,8 +22,13 @@ namespace npw {
 // SHARE: the per-cell weight denominators and k = 2 shape parameters go through LDS and serve both
 // interfaces of a cell; otherwise every interface recomputes them (less LDS, more workgroups per
 // compute unit).  The switch flags and ENO stencils are shared either way.
+// Occupancy: the float Euler kernel with both fused sweeps (62-wide tiles, k = 3, component-wise) is
+// held to 6 waves per SIMD, the most its LDS allows: left alone the compiler takes 82 VGPRs, which
+// allocate as 88 and leave room for 5 (measured on 2048^2 Euler: 132.1 us per stage at 6 waves with
+// a 12-byte spill, 134.6 us at 5).  Every other instantiation keeps the compiler's choice.
 template <typename R, int FLUX, int M, int TX, int TY, bool CHAR = false, bool K2 = true, bool SHARE = true>
-__global__ __launch_bounds__(256) void stage2d_kernel(StageArgs a) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(
+    (sizeof(R) == 4 && M == 4 && TX + 2 == 64 && !CHAR && !K2 && !SHARE) ? 6 : 1))) void stage2d_kernel(StageArgs a) {
   constexpr int BS = 256;
   constexpr bool kExact = std::is_same<R, double>::value;
   constexpr int WX = TX + 6, WY = TY + 6;                          // staged cells per row / column
@@ -266,17 +271,19 @@ __global__ __launch_bounds__(256) void stage2d_kernel(StageArgs a) {
           for (int c = 0; c < M; ++c) {
             const R u0 = U(c, line, q - 2), u1 = U(c, line, q - 1), u2 = U(c, line, q), u3 = U(c, line, q + 1),
                     u4 = U(c, line, q + 2);
-            const int fl = use_switch ? monotone_flag<kExact>(double(u1), double(u2), double(u3)) : 0;
+            const double d1 = double(u1), d2 = double(u2), d3 = double(u3), d4 = double(u4);
+            const int fl = use_switch ? monotone_flag<kExact>(d1, d2, d3) : 0;
             const int fl_next = __shfl_down(fl, 1);
-            double e = 0.0;
+            // the double shape parameter, rounded to the bulk type, then zeroed by the switch
+            R eta_r = R(0);
             if (use_eta) {
-              e = eta_ratio<kExact>(double(u1), double(u2), double(u3), double(u4), eps_m);
-              if (use_switch && ((fl | fl_next) & 1)) e = 0.0;
+              eta_r = R(eta_ratio<kExact>(d1, d2, d3, d4, eps_m));
+              if (use_switch && ((fl | fl_next) & 1)) eta_r = R(0);
             }
-            const R eta_r = R(e), eta_l = __shfl_up(eta_r, 1);
+            const R eta_l = __shfl_up(eta_r, 1);
             R vm, vp;
             if (eno) {
-              const int r = eno_stencil(double(u0), double(u1), double(u2), double(u3), double(u4));
+              const int r = eno_stencil(double(u0), d1, d2, d3, d4);
               vm = eno_minus<R>(r, u0, u1, u2, u3, u4, eta_r);
               vp = eno_plus<R>(r, u0, u1, u2, u3, u4, eta_l);
             } else {
@@ -312,24 +319,25 @@ __global__ __launch_bounds__(256) void stage2d_kernel(StageArgs a) {
         R vp[LEN + 1];
         int fl_prev = 0, r_prev = 0;
         R d0p = R(0), d1p = R(0), d2p = R(0);
+        // the window of cell j (cells j-2 .. j+2, the left neighbour's farthest cell j-3) and the
+        // doubles of cells j-2 .. j+1, carried from step to step: one new cell per step
+        R z = R(0), ua = V(-3), ub = V(-2), uc = V(-1), ud = V(0), ue = V(1);
+        double da = double(ua), db = double(ub), dc = double(uc), dd = double(ud);
 #pragma unroll
         for (int j = -1; j <= LEN; ++j) {
-          const R ua = V(j - 2), ub = V(j - 1), uc = V(j), ud = V(j + 1), ue = V(j + 2);
-          const int fl = use_switch ? monotone_flag<kExact>(double(ub), double(uc), double(ud)) : 0;
+          const int fl = use_switch ? monotone_flag<kExact>(db, dc, dd) : 0;
           int r = 0;
           R d0 = R(0), d1 = R(0), d2 = R(0);
           if (eno)
-            r = eno_stencil(double(ua), double(ub), double(uc), double(ud), double(ue));
+            r = eno_stencil(da, db, dc, dd, double(ue));
           else
             weight_denominators<R>(ua, ub, uc, ud, ue, eps, d0, d1, d2);
-          if (j >= 0) {  // interface j - 1/2 between cells j - 1 and j
-            const R z = V(j - 3);  // the left cell's farthest neighbour (staged rows start at j = -3)
-            double e = 0.0;
+          if (j >= 0) {  // interface j - 1/2 between cells j - 1 and j; z is cell j - 3
+            R eta = R(0);
             if (use_eta) {
-              e = eta_ratio<kExact>(double(ua), double(ub), double(uc), double(ud), eps_m);
-              if (use_switch && ((fl_prev | fl) & 1)) e = 0.0;
+              eta = R(eta_ratio<kExact>(da, db, dc, dd, eps_m));
+              if (use_switch && ((fl_prev | fl) & 1)) eta = R(0);
             }
-            const R eta = R(e);
             R vm;
             if (eno) {
               vm = eno_minus<R>(r_prev, z, ua, ub, uc, ud, eta);
@@ -345,6 +353,18 @@ __global__ __launch_bounds__(256) void stage2d_kernel(StageArgs a) {
           d0p = d0;
           d1p = d1;
           d2p = d2;
+          if (j < LEN) {  // slide the window up one cell (the staged column ends at cell LEN + 2)
+            z = ua;
+            ua = ub;
+            ub = uc;
+            uc = ud;
+            ud = ue;
+            ue = V(j + 3);
+            da = db;
+            db = dc;
+            dc = dd;
+            dd = double(ud);
+          }
         }
 #pragma unroll
         for (int k = 0; k < NOWN; ++k) {
@@ -467,13 +487,12 @@ __global__ __launch_bounds__(256) void stage2d_kernel(StageArgs a) {
           }
           continue;
         }
-        double e = 0.0;
+        R eta = R(0);
         if (use_eta) {
-          e = eta_ratio<kExact>(double(U(c, line, q - 1)), double(U(c, line, q)), double(U(c, line, q + 1)),
-                        double(U(c, line, q + 2)), eps_m);
-          if (use_switch && ((FL(c, wl) | FL(c, wr)) & 1)) e = 0.0;
+          eta = R(eta_ratio<kExact>(double(U(c, line, q - 1)), double(U(c, line, q)), double(U(c, line, q + 1)),
+                                    double(U(c, line, q + 2)), eps_m));
+          if (use_switch && ((FL(c, wl) | FL(c, wr)) & 1)) eta = R(0);
         }
-        const R eta = R(e);
         if (eno) {
           A[c] = eno_minus<R>(FL(c, wl) >> 1, U(c, line, q - 2), U(c, line, q - 1), U(c, line, q),
                               U(c, line, q + 1), U(c, line, q + 2), eta);
