@@ -217,7 +217,8 @@ int npweno_launch_shape(const npw_solver* s, int32_t* block_1d, int32_t* tile_x,
  * bit-identical to solving it alone with npweno_create/npweno_solve in the same precision.
  * Requests never fail one another: a request that becomes non-finite or non-physical is
  * retired with its error and last good state. */
-/* max_slots in [1, 65536]; precision NPW_FP32 or NPW_FP64 for every request; hbm_budget_bytes at
+/* The pools step with workgroups of 256 threads (NPW_BLOCK = 64, 128, 256 or 512 overrides).
+ * max_slots in [1, 65536]; precision NPW_FP32 or NPW_FP64 for every request; hbm_budget_bytes at
  * least 3 * 256 elements.  hip_stream is not used: requests enter and leave as host copies, and the
  * server works on private streams of its own (pass NULL). */
 int npw_server_create(size_t hbm_budget_bytes, int32_t max_slots, int32_t precision, void* hip_stream,
@@ -233,7 +234,8 @@ int npw_server_pump(npw_server* srv, int32_t steps, int32_t* n_running, int32_t*
 /* NPW_EBUSY until the request finished; then copies its final state (the last good state and
  * the error code if it failed) and its stats. */
 int npw_server_poll(npw_server* srv, uint64_t req_id, void* u_out_host, npw_stats* stats);
-/* Host steady-clock times (seconds) of submission, admission and completion. */
+/* Host steady-clock times (seconds) of submission, admission and completion (any output pointer
+ * may be NULL).  Returns NPW_EBUSY until the request finished, NPW_OK after; copies no state. */
 int npw_server_times(const npw_server* srv, uint64_t req_id, double* t_submit, double* t_admit, double* t_done);
 /* Drop the stored result of a finished request. */
 int npw_server_release(npw_server* srv, uint64_t req_id);

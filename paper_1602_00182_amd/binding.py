@@ -370,6 +370,14 @@ class Server:
         lib().npw_server_times(self.h, rid, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c))
         return a.value, b.value, c.value
 
+    def finished(self, rid: int) -> bool:
+        """True once the request has finished (npw_server_times stops returning NPW_EBUSY); copies
+        nothing."""
+        rc = lib().npw_server_times(self.h, rid, None, None, None)
+        if rc not in (OK, EBUSY):
+            raise NpwError(rc, "npw_server_times")
+        return rc == OK
+
     def release(self, rid: int):
         lib().npw_server_release(self.h, rid)
 
