@@ -106,8 +106,8 @@ def counter_traffic(kernel: str):
 
 
 def counter_valu(kernel: str):
-    """VALU issue utilisation of `kernel` (SQ_INSTS_VALU over 256 CUs x 2.4 GHz x duration) from the
-    VALU counter summaries under profiles/, or None when none covers this kernel as now built."""
+    """VALU wave-instructions per launch of `kernel` and their split into instruction classes, from
+    the VALU counter summaries under profiles/, or None when none covers this kernel as now built."""
     key = "kernel=" + kernel.replace(" ", "")
     src = "source=" + kernel_source_hash()
     pdir = os.path.join(ROOT, "profiles")
@@ -120,8 +120,73 @@ def counter_valu(kernel: str):
             for line in f:
                 parts = line.split()
                 if parts and parts[0] == "valu" and key in parts and src in parts:
-                    return float(next(p for p in parts if p.startswith("utilisation="))[len("utilisation="):])
+                    kv = dict(p.split("=", 1) for p in parts[1:] if "=" in p)
+                    if "classes" not in kv:
+                        return None
+                    classes = {c: float(v) for c, v in (x.split(":") for x in kv["classes"].split(","))}
+                    return {"wave_instr_per_launch": float(kv["wave_instr_per_launch"]),
+                            "wave_instr_per_cell_stage": float(kv["wave_instr_per_cell_stage"]),
+                            "classes": classes, "summary": name}
     return None
+
+
+# The counters split compares, selects, moves and bit logic into no classes of their own; the probe
+# replays that remainder in the proportions of the 2D Euler stage's code (compares 6, selects 8,
+# moves 4, logic 3).
+REST_SPLIT = {"cmp": 6.0, "cnd": 8.0, "mov": 4.0, "logic": 3.0}
+_CEILINGS = {}
+
+
+def probe_argv(classes: dict) -> list:
+    """valu_mix_probe arguments for counted instruction classes (the remainder split by REST_SPLIT)."""
+    mix = {k: v for k, v in classes.items() if k != "rest"}
+    rest = classes.get("rest", 0.0)
+    tot = sum(REST_SPLIT.values())
+    for k, w in REST_SPLIT.items():
+        mix[k] = mix.get(k, 0.0) + rest * w / tot
+    return [f"{k}={v:.3f}" for k, v in sorted(mix.items()) if v > 0]
+
+
+def valu_ceiling(classes: dict):
+    """Wave-instructions per second that the whole GPU sustains on this instruction mix, measured
+    by the valu_mix_probe program (built beside the library), or None if it cannot run."""
+    import subprocess
+    argv = probe_argv(classes)
+    key = " ".join(argv)
+    if key not in _CEILINGS:
+        exe = os.path.join(ROOT, "paper_1602_00182_amd", "valu_mix_probe")
+        try:
+            r = subprocess.run([exe, *argv], capture_output=True, text=True, timeout=120)
+            _CEILINGS[key] = json.loads(r.stdout.strip().splitlines()[-1]) if r.returncode == 0 else None
+            if r.returncode != 0:
+                progress(f"valu_mix_probe failed ({r.returncode}): {r.stderr.strip()[-200:]}")
+        except (OSError, subprocess.TimeoutExpired, ValueError, IndexError) as e:
+            progress(f"valu_mix_probe did not run: {e}")
+            _CEILINGS[key] = None
+    return _CEILINGS[key]
+
+
+def valu_roof(label: str, avg_launch: float = None, cell_stages_per_s: float = None):
+    """Issue rate of the kernel's VALU instructions against the ceiling of its own mix.  The counters
+    give the instructions of one launch (and per cell-stage); this run's event timing gives the rate:
+    per launch over the average launch, or per cell-stage times the cell-stages done per second
+    (batches, whose launches narrow as instances finish)."""
+    c = counter_valu(label)
+    if c is None:
+        return None
+    ceil = valu_ceiling(c["classes"])
+    if cell_stages_per_s is not None:
+        rate = c["wave_instr_per_cell_stage"] * cell_stages_per_s
+    else:
+        rate = c["wave_instr_per_launch"] / avg_launch
+    out = {"issue_rate": rate, "unit": "wave-instructions/s", "wave_instr_per_launch": c["wave_instr_per_launch"],
+           "wave_instr_per_cell_stage": c["wave_instr_per_cell_stage"], "counters": c["summary"]}
+    if ceil is not None:
+        out.update({"ceiling": ceil["wave_instr_per_s"], "frac": rate / ceil["wave_instr_per_s"],
+                    "ceiling_mix_per_200": ceil["mix_per_round"],
+                    "ceiling_basis": "valu_mix_probe: the kernel's counted VALU mix replayed with no memory "
+                                     "traffic or dependency stalls, best of 8/6/4 register chains"})
+    return out
 
 
 def alg_flops_per_cell_stage(w) -> float:
@@ -284,7 +349,7 @@ def roofline(w, label, cells_per_launch, esize, avg_launch, traffic=None):
            "bytes_per_launch": bytes_per_launch}
     alu = {"achieved": tflops, "peak": ALU_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": tflops / ALU_PEAK_TFLOPS,
            "flops_per_launch": flops, "flops_per_cell_stage": alg_flops_per_cell_stage(w)}
-    common = {"traffic": traffic, "valu_issue_utilisation": counter_valu(label), "kernel": label,
+    common = {"traffic": traffic, "valu": valu_roof(label, avg_launch), "kernel": label,
               "avg_launch_us": avg_launch * 1e6}
     if w.dim == 2 or w.flux == 2:
         return {"bound": "alu", **{k: alu[k] for k in ("achieved", "peak", "unit", "frac")}, **common,
@@ -508,7 +573,7 @@ def bench_batch(args, prec):
                          "frac": tflops / ALU_PEAK_TFLOPS, "traffic": counter_traffic(label),
                          "traffic_note": "HBM bytes per launch while every instance is running (counters over "
                                          "the first 20 steps)",
-                         "valu_issue_utilisation": counter_valu(label), "kernel": label,
+                         "valu": valu_roof(label, cell_stages_per_s=total_cell_stages / gpu_s), "kernel": label,
                          "peak_basis": "FP32 vector FMA without packed-FP32 instructions",
                          "hbm": {"achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                                  "frac": achieved / HBM_PEAK_GBS},

@@ -15,6 +15,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 LIB = os.path.join(HERE, "libnpweno.so")
+# stand-alone program that measures the VALU issue ceiling of an instruction mix (bench.py runs it)
+PROBE = os.path.join(HERE, "valu_mix_probe")
 BUILD = os.path.join(HERE, "_build")
 
 ARCH = os.environ.get("NPW_OFFLOAD_ARCH", "gfx950")
@@ -47,10 +49,21 @@ def _compile(unit, extra):
     return obj
 
 
+def _build_probe():
+    tmp = PROBE + ".tmp"
+    cmd = [_hipcc(), *COMMON, os.path.join(CSRC, "valu_mix_probe.hip"), "-o", tmp]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"hipcc failed for valu_mix_probe.hip:\n{r.stderr}")
+    os.replace(tmp, PROBE)
+
+
 def build(verbose: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
-    with ThreadPoolExecutor(max_workers=len(UNITS)) as ex:
+    with ThreadPoolExecutor(max_workers=len(UNITS) + 1) as ex:
+        probe = ex.submit(_build_probe)
         objs = list(ex.map(lambda u: _compile(*u), UNITS))
+        probe.result()
     tmp = LIB + ".tmp"
     cmd = [_hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -58,7 +71,7 @@ def build(verbose: bool = False) -> str:
         raise RuntimeError(f"link failed:\n{r.stderr}")
     os.replace(tmp, LIB)
     if verbose:
-        print("built", LIB)
+        print("built", LIB, "and", PROBE)
     return LIB
 
 

@@ -64,12 +64,30 @@ def test_counter_valu_requires_matching_kernel_and_source(tmp_path, monkeypatch)
     pdir = tmp_path / "profiles"
     pdir.mkdir()
     (pdir / "k_valu_counters.txt").write_text(
-        f"# header\nvalu kernel=stage2d_kernel<float,Euler,4,64,8,recompute> source={h} utilisation=0.896 "
-        f"wave_instr_per_cell_stage=26.1\n")
+        f"# header\nvalu kernel=stage2d_kernel<float,Euler,4,64,8,recompute> source={h} wave_instr_per_launch=9.0e7 "
+        f"wave_instr_per_cell_stage=21.5 classes=fma32:300.0,int32:100.0,rest:200.0\n"
+        f"valu kernel=stage2d_kernel<float,Euler,4,62,8,recompute> source=0000000000000000 wave_instr_per_launch=1 "
+        f"wave_instr_per_cell_stage=1 classes=fma32:1\n")
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
     monkeypatch.setattr(bench, "kernel_source_hash", lambda: h)
-    assert bench.counter_valu("stage2d_kernel<float, Euler, 4, 64, 8, recompute>") == pytest.approx(0.896)
+    got = bench.counter_valu("stage2d_kernel<float, Euler, 4, 64, 8, recompute>")
+    assert got["wave_instr_per_launch"] == 9.0e7 and got["wave_instr_per_cell_stage"] == 21.5
+    assert got["classes"] == {"fma32": 300.0, "int32": 100.0, "rest": 200.0}
+    # a summary of another kernel build does not count
     assert bench.counter_valu("stage2d_kernel<float, Euler, 4, 62, 8, recompute>") is None
+
+
+def test_probe_argv_splits_the_remainder():
+    """The counters leave compares, selects, moves and logic in one remainder; the probe gets it
+    split in fixed proportions, and every other class as counted."""
+    import bench
+    argv = bench.probe_argv({"fma32": 300.0, "int32": 100.0, "rest": 210.0})
+    mix = {a.split("=")[0]: float(a.split("=")[1]) for a in argv}
+    tot = sum(bench.REST_SPLIT.values())
+    assert mix["fma32"] == 300.0 and mix["int32"] == 100.0 and "rest" not in mix
+    for k, w in bench.REST_SPLIT.items():
+        assert mix[k] == pytest.approx(210.0 * w / tot, abs=1e-3)
+    assert sum(mix.values()) == pytest.approx(610.0, abs=1e-2)
 
 
 def test_oracle_worker_and_all_core_baseline():
