@@ -3,6 +3,7 @@ import os
 import subprocess
 import sys
 
+import numpy as np
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -125,3 +126,14 @@ def test_roofline_bound_per_workload():
     r1 = bench.roofline(w1, "k", w1.ncell, 4, 2e-6, traffic=5.0)
     assert r1["bound"] == "hbm" and r1["unit"] == "GB/s" and r1["traffic"] == 5.0
     assert r1["achieved"] == pytest.approx(8 / 3 * 4 * 4096 / 2e-6 / 1e9)
+
+
+def test_smooth_mask_excludes_the_neighbourhood_of_jumps():
+    import bench
+    n = 40
+    u = np.where(np.arange(n) < 20, 1.0, 0.2) + 1e-4 * np.sin(np.arange(n) / 7.0)
+    m = bench.smooth_mask(u, 1, (n,))
+    # the jump between cells 19 and 20 marks both as rough; 4 cells either side go too
+    assert not m[15:25].any() and m[:15].all() and m[25:].all()
+    two = np.stack([u, np.ones(n)])
+    assert np.array_equal(bench.smooth_mask(two.reshape(-1), 2, (n,)), m)

@@ -294,3 +294,28 @@ def test_weno_reconstruction_exact_for_quadratics():
     u5 = np.array([m * m + m + 1.0 / 3.0 for m in range(-2, 3)])
     assert O.recon_minus(u5, 0.0) == pytest.approx(1.0, abs=1e-12)
     assert O.recon_plus(u5, 0.0) == pytest.approx(0.0, abs=1e-12)
+
+
+def test_quotient_free_switch_form_agrees_on_float_data():
+    """The float-bulk kernels decide the Section 4 switch without forming the quotient: with
+    p = u_i - u_{i-1} and q = u_{i+1} - u_i in double, the printed 0 < x_p < 3 holds exactly when
+    p - q, 2p - q and p - 2q are non-zero with one sign (the sign of p - q against those of the
+    other two, as two products).  On float data that equals the oracle's rounded-quotient test:
+    random windows, windows with ties and near-ties planted, and windows spanning wide exponent
+    ranges."""
+    rng = np.random.default_rng(12)
+
+    def quotient_free(a, b, c):
+        p, q = b - a, c - b
+        t1 = p - q
+        t2, t3 = p + t1, t1 - q
+        return int(t1 * t2 > 0.0 and t1 * t3 > 0.0)
+
+    wins = [rng.standard_normal(3) for _ in range(20000)]
+    wins += [rng.integers(-6, 7, 3).astype(float) * rng.choice([1e-3, 0.37, 1.0, 2.0 ** 40]) for _ in range(20000)]
+    wins += [np.array([a, b, c], float) * s + o for a, b, c, _ in _tie_windows()
+             for s in (1.0, 0.1, 3.7e5) for o in (0.0, 1.25, -1e3)]
+    wins += [np.exp(rng.uniform(-80, 80, 3)) * rng.choice([-1.0, 1.0], 3) for _ in range(20000)]
+    for w in wins:
+        a, b, c = (float(np.float32(x)) for x in w)  # float data, widened exactly
+        assert quotient_free(a, b, c) == O.monotone_flag(a, b, c), (a, b, c)
