@@ -254,12 +254,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(
     auto U = [&](int c, int line, int q) -> R { return DIR == 0 ? s_u[c][line + 3][q] : s_u[c][q][line + 3]; };
     auto cid = [&](int line, int pos) -> int { return DIR == 0 ? line * NPOS + pos + 1 : (pos + 1) * LINES + line; };
     // x sweep with one wave per row, for tiles whose staged row holds cells -1..TX in exactly one
-    // wave: lane l takes cell p = l - 1 and forms its flag, weight denominators, eta_{p+1/2} and
-    // both edge values once; the next cell's flag, eta_{p-1/2} and v^+_{p+1/2} arrive by lane
-    // shuffles.  Same functions on the same operands as the two phases below: the double bulk's
-    // fluxes are identical bit for bit (the float bulk's up to how multiply-adds are fused); the
-    // separate flag pass and its barrier go away, and so does the second denominator set of every
-    // interface.
+    // wave: lane l takes cell p = l - 1, forms its flag and weight denominators once, and then the
+    // interface p+1/2 whole (eta, v^- of cell p, v^+ of cell p+1); the next cell's flag and weight
+    // denominators arrive by lane shuffles.  Same functions on the same operands as the two phases
+    // below: the double bulk's fluxes are identical bit for bit (the float bulk's up to how
+    // multiply-adds are fused); the separate flag pass and its barrier go away, and so does the
+    // second denominator set of every interface.
     bool rows = false;
     if constexpr (DIR == 0 && kRowWave) {
       rows = !cross;
@@ -269,8 +269,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(
           R A[M], B[M], H[M];
 #pragma unroll
           for (int c = 0; c < M; ++c) {
+            // u5 = cell p + 3 (the last lane's interface is not used; its read stays in the row)
             const R u0 = U(c, line, q - 2), u1 = U(c, line, q - 1), u2 = U(c, line, q), u3 = U(c, line, q + 1),
-                    u4 = U(c, line, q + 2);
+                    u4 = U(c, line, q + 2), u5 = U(c, line, lane < 63 ? q + 3 : q + 2);
             const double d1 = double(u1), d2 = double(u2), d3 = double(u3), d4 = double(u4);
             const int fl = use_switch ? monotone_flag<kExact>(d1, d2, d3) : 0;
             const int fl_next = __shfl_down(fl, 1);
@@ -280,20 +281,24 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(
               eta_r = R(eta_ratio<kExact>(d1, d2, d3, d4, eps_m));
               if (use_switch && ((fl | fl_next) & 1)) eta_r = R(0);
             }
-            const R eta_l = __shfl_up(eta_r, 1);
+            // both edge values of interface p+1/2: v^- of cell p and v^+ of cell p+1 (window
+            // u1..u5, its stencil or weight denominators from the next lane); they share eta and
+            // two of their three substencil values
             R vm, vp;
             if (eno) {
               const int r = eno_stencil(double(u0), d1, d2, d3, d4);
+              const int r_next = __shfl_down(r, 1);
               vm = eno_minus<R>(r, u0, u1, u2, u3, u4, eta_r);
-              vp = eno_plus<R>(r, u0, u1, u2, u3, u4, eta_l);
+              vp = eno_plus<R>(r_next, u1, u2, u3, u4, u5, eta_r);
             } else {
-              R d0, d1, d2;
-              weight_denominators<R>(u0, u1, u2, u3, u4, eps, d0, d1, d2);
-              vm = weno_minus<R>(u0, u1, u2, u3, u4, eta_r, d0, d1, d2);
-              vp = weno_plus<R>(u0, u1, u2, u3, u4, eta_l, d0, d1, d2);
+              R s0, s1, s2;
+              weight_denominators<R>(u0, u1, u2, u3, u4, eps, s0, s1, s2);
+              const R n0 = __shfl_down(s0, 1), n1 = __shfl_down(s1, 1), n2 = __shfl_down(s2, 1);
+              vm = weno_minus<R>(u0, u1, u2, u3, u4, eta_r, s0, s1, s2);
+              vp = weno_plus<R>(u1, u2, u3, u4, u5, eta_r, n0, n1, n2);
             }
             A[c] = vm;
-            B[c] = __shfl_down(vp, 1);
+            B[c] = vp;
           }
           lf_flux<R, FLUX, M, 0>(A, B, alpha_x, speed_x, gamma, H);
           if (lane < 63) {
