@@ -23,9 +23,10 @@ namespace npw {
 // interfaces of a cell; otherwise every interface recomputes them (less LDS, more workgroups per
 // compute unit).  The switch flags and ENO stencils are shared either way.
 // Occupancy: the float Euler kernel with both fused sweeps (62-wide tiles, k = 3, component-wise) is
-// held to 6 waves per SIMD, the most its LDS allows: left alone the compiler takes 82 VGPRs, which
-// allocate as 88 and leave room for 5 (measured on 2048^2 Euler: 132.1 us per stage at 6 waves with
-// a 12-byte spill, 134.6 us at 5).  Every other instantiation keeps the compiler's choice.
+// held to 6 waves per SIMD, the most its LDS allows (80 VGPRs at most).  It fits in 78 without
+// spilling; the hint keeps a later change from sliding to 5 waves unnoticed (an earlier form needed
+// 82, which allocate as 88: 134.6 us per stage at 5 waves against 132.1 us at 6 with a 12-byte
+// spill, on 2048^2 Euler).  Every other instantiation keeps the compiler's choice.
 template <typename R, int FLUX, int M, int TX, int TY, bool CHAR = false, bool K2 = true, bool SHARE = true>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(
     (sizeof(R) == 4 && M == 4 && TX + 2 == 64 && !CHAR && !K2 && !SHARE) ? 6 : 1))) void stage2d_kernel(StageArgs a) {
