@@ -198,7 +198,8 @@ int npweno_get_stats_instance(const npw_solver* s, int32_t index, npw_stats* sta
 int npweno_instance_count(const npw_solver* s);
 /* Launch shape the solver uses for its stage kernel (picked at create by the autotuner, or set by
  * NPW_BLOCK / NPW_TILE2D): *block_1d = threads per workgroup of the 1D kernel (64, 128, 256 or 512),
- * *tile_x, *tile_y = interior cells per workgroup of the 2D kernel (0 for a 1D solver), and
+ * *tile_x, *tile_y = interior cells per workgroup of the 2D kernel (0 for a 1D solver; a tile_y
+ * above 8 is a column strip that the workgroup walks 4 rows at a time, 2D Euler only), and
  * *lds_shared = 1 when the 2D kernel shares per-cell weight denominators through LDS, 0 when every
  * interface recomputes them (always 0 for characteristic-wise 2D, always 1 in 1D).  Any output pointer may be NULL.  Host-only;
  * returns NPW_EINVAL for a NULL solver. */

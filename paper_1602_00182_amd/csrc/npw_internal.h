@@ -93,8 +93,10 @@ hipError_t launch_stage_f32(int flux, int ncomp, int block, const StageArgs& a, 
 // slower on 2048^2 Euler: 211 and 251 us per stage against 193 us for 64 x 8.  Recomputed 63 x 8,
 // whose x sweep fills exactly 8 waves, measured the same as 64 x 8 (187.8-188.6 us); 127 x 4 took
 // 250 us.  With the one-wave-per-row x sweep, a 62 x 16 tile on 512 threads took 160.4 us against
-// 153.5 us for 62 x 8.)
-constexpr int k2dShapes = 6;
+// 153.5 us for 62 x 8.)  6, 7, 8 = column strips of 62 x 16, 32 and 64 cells walked in 4-row
+// chunks (2D Euler, component-wise k = 3; every other scheme runs shape 4 for them).
+constexpr int k2dShapes = 9;
+constexpr int k2dStripFirst = 6;
 hipError_t launch_stage2d_f64(int flux, int ncomp, int shape, const StageArgs& a, hipStream_t s);
 hipError_t launch_stage2d_f32(int flux, int ncomp, int shape, const StageArgs& a, hipStream_t s);
 // State check of u^n for ninst instances: alpha slot 0 (and the spread entries of a single grid),

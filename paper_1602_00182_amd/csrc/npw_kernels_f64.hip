@@ -1,6 +1,7 @@
 // Kernel instantiations for the double bulk precision.
 #include "npw_kernels.h"
 #include "npw_kernels2d.h"
+#include "npw_kernels2d_strip.h"
 
 namespace npw {
 
@@ -60,6 +61,16 @@ static hipError_t launch2d(int flux, int ncomp, const StageArgs& a, hipStream_t 
                   : launch2d_k<TX, TY, false, SHARE>(flux, ncomp, a, s);
 }
 
+// 2D Euler column strips of H rows (component-wise k = 3 only; other schemes take the 62 x 8 tile
+// with per-interface denominators, whose sweeps the strip kernel shares).
+template <int H>
+static hipError_t launch2d_strip(int flux, int ncomp, const StageArgs& a, hipStream_t s) {
+  if (flux != kEuler || ncomp != 4 || a.charw || a.any_k2) return launch2d<62, 8, false>(flux, ncomp, a, s);
+  const dim3 grid((unsigned)((a.nx + kStripTX - 1) / kStripTX), (unsigned)((a.ny + H - 1) / H)), block(256);
+  stage2d_strip_kernel<double, kEuler, H><<<grid, block, 0, s>>>(a);
+  return hipGetLastError();
+}
+
 hipError_t launch_stage2d_f64(int flux, int ncomp, int shape, const StageArgs& a, hipStream_t s) {
   switch (shape) {
     case 0: return launch2d<64, 8, true>(flux, ncomp, a, s);
@@ -68,6 +79,9 @@ hipError_t launch_stage2d_f64(int flux, int ncomp, int shape, const StageArgs& a
     case 3: return launch2d<64, 8, false>(flux, ncomp, a, s);
     case 4: return launch2d<62, 8, false>(flux, ncomp, a, s);
     case 5: return launch2d<126, 4, false>(flux, ncomp, a, s);
+    case 6: return launch2d_strip<16>(flux, ncomp, a, s);
+    case 7: return launch2d_strip<32>(flux, ncomp, a, s);
+    case 8: return launch2d_strip<64>(flux, ncomp, a, s);
     default: return hipErrorInvalidValue;
   }
 }

@@ -762,11 +762,14 @@ int npweno_instance_count(const npw_solver* s) { return s ? s->ninst : 0; }
 static int npweno_launch_shape_impl(const npw_solver* s, int32_t* block_1d, int32_t* tile_x, int32_t* tile_y,
                         int32_t* lds_shared) {
   if (!s) return NPW_EINVAL;
-  static const int kTx[npw::k2dShapes] = {64, 62, 126, 64, 62, 126};
-  static const int kTy[npw::k2dShapes] = {8, 8, 4, 8, 8, 4};
+  static const int kTx[npw::k2dShapes] = {64, 62, 126, 64, 62, 126, 62, 62, 62};
+  static const int kTy[npw::k2dShapes] = {8, 8, 4, 8, 8, 4, 16, 32, 64};
+  // the strips run only 2D Euler with component-wise k = 3; other schemes take the 62 x 8 tile
+  const bool strip_ok = s->flux == npw::kEuler && s->ncomp == 4 && !s->charw && !s->any_k2;
+  const int shape = s->shape2d >= npw::k2dStripFirst && !strip_ok ? 4 : s->shape2d;
   if (block_1d) *block_1d = s->block;
-  if (tile_x) *tile_x = s->dim == 2 ? kTx[s->shape2d] : 0;
-  if (tile_y) *tile_y = s->dim == 2 ? kTy[s->shape2d] : 0;
+  if (tile_x) *tile_x = s->dim == 2 ? kTx[shape] : 0;
+  if (tile_y) *tile_y = s->dim == 2 ? kTy[shape] : 0;
   // characteristic-wise 2D reconstruction works per interface and shares nothing per cell
   if (lds_shared) *lds_shared = s->dim == 2 ? (s->shape2d < 3 && !s->charw ? 1 : 0) : 1;
   return NPW_OK;
