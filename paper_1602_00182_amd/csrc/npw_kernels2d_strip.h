@@ -39,20 +39,23 @@ constexpr int kStripTX = 62;  // owned columns of a strip (cells -1..62 of a row
 constexpr int kStripCH = 4;   // rows per chunk (one per wave in the x sweep and the update)
 
 // H = rows of a strip (a multiple of kStripCH).  Euler, four components, k = 3 component-wise.
-// Float: held to 5 waves per SIMD (96 vector registers).  At 6 (80 registers) it spills 28 bytes
-// per lane, and on 2048^2 Euler the 16-row strip took 128.3 us per stage at 6 waves against 125.0 us
-// at 5 (the 62 x 8 tile kernel: 126.0 us).
+// Float: 6 waves per SIMD, the most its 24 KB of LDS allows; it needs 77 vector registers because
+// nothing is held across the chunk loop but the march's previous-cell flag and weight denominators,
+// the running spectral radii and the lane index (made opaque each chunk), and the next chunk's
+// rows travel from memory to LDS without registers.
 template <typename R, int FLUX, int H>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 5 : 1))) void
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 6 : 1))) void
 stage2d_strip_kernel(StageArgs a) {
   constexpr int M = 4, BS = 256, TX = kStripTX, CH = kStripCH;
   constexpr int WX = TX + 6;     // staged cells per row: -3..TX+2
-  constexpr int RING = 12;       // staged rows: chunk rows, and the rows the column march reads ahead
+  // staged rows: the chunk's rows, the rows the column march reads ahead, and the next chunk's four
+  // rows, which are loaded a whole chunk ahead into the slots of rows no longer read
+  constexpr int RING = 13;
   constexpr bool kExact = std::is_same<R, double>::value;
   static_assert(H % CH == 0 && M * 64 == BS, "one wave per component, one row per wave");
   __shared__ R s_u[M][RING][WX];
-  // y interfaces of the chunk, slot s = interface jk + s - 1/2 (s = 0..CH): v^- (then the flux
-  // G, in place) and v^+; slot 0 carries the previous chunk's top flux
+  // y interfaces jk + s - 1/2 (s = 0..CH) of chunk k sit in slot (CH k + s) mod (CH + 1): v^- (then
+  // the flux G, in place) and v^+; a chunk's top flux slot is the next chunk's bottom one
   __shared__ R s_vm[M][CH + 1][TX];
   __shared__ R s_vp[M][CH + 1][TX];
   __shared__ unsigned long long s_red[2][BS / 64];
@@ -219,6 +222,30 @@ stage2d_strip_kernel(StageArgs a) {
   const R dx = scalar_reg(R(dxd)), dy = scalar_reg(R(dyd));
   const R inv_dx = scalar_reg(R(I->inv_dx)), inv_dy = scalar_reg(R(I->inv_dy));
 
+  // The same for a row that is first read in the next chunk.  Float rows inside the grid go
+  // straight from memory to LDS (no registers; the loads complete under the chunk's work and are
+  // waited for before the chunk's last barrier); other rows take the path above.
+  auto stage_row_ahead = [&](int row) {
+    if constexpr (sizeof(R) == 4) {
+      if (cols_in && row >= 0 && row < ny) {
+        const __amdgpu_buffer_rsrc_t rs = buffer_of(src, state_bytes);
+        const int sl = slot_of(row);
+        const unsigned at = ((unsigned)row * (unsigned)nx + (unsigned)(i0 - 3 + lane)) * sizeof(R);
+#pragma unroll
+        for (int c = 0; c < M; ++c)
+          __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (__attribute__((address_space(3))) void*)&s_u[c][sl][0], 4,
+                                                   at, c * comp_bytes, 0, 0);
+        if (lane < WX - 64) {
+#pragma unroll
+          for (int c = 0; c < M; ++c)
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (__attribute__((address_space(3))) void*)&s_u[c][sl][64], 4,
+                                                     at + 64u * (unsigned)sizeof(R), c * comp_bytes, 0, 0);
+        }
+        return;
+      }
+    }
+    stage_row(row);
+  };
   // rows of this strip inside the grid, in whole chunks
   const int rows = H < ny - j0 ? H : ny - j0;
   const int nchunk = (rows + CH - 1) / CH;
@@ -247,8 +274,8 @@ stage2d_strip_kernel(StageArgs a) {
   int fl_prev = 0, r_prev = 0;
   R d0p = R(0), d1p = R(0), d2p = R(0);
   // one step of the march at cell j: its flag and weight denominators, and (from cell j0 on) the
-  // interface j - 1/2, whose v^- and v^+ go to slot j - jk; then slide the window up one cell
-  auto march = [&](int j, int jk) {
+  // interface j - 1/2, whose v^- and v^+ go to flux slot `fs`; then slide the window up one cell
+  auto march = [&](int j, int fs) {
     const int fl = use_switch ? monotone_flag<kExact>(db, dc, dd) : 0;
     int r = 0;
     R e0 = R(0), e1 = R(0), e2 = R(0);
@@ -271,8 +298,8 @@ stage2d_strip_kernel(StageArgs a) {
         vp = weno_plus<R>(ua, ub, uc, ud, ue, eta, e0, e1, e2);
       }
       if (lane < TX) {
-        s_vm[mc][j - jk][lane] = vm;
-        s_vp[mc][j - jk][lane] = vp;
+        s_vm[mc][fs][lane] = vm;
+        s_vp[mc][fs][lane] = vp;
       }
     }
     fl_prev = fl;
@@ -291,7 +318,7 @@ stage2d_strip_kernel(StageArgs a) {
     dc = dd;
     dd = double(ud);
   };
-  march(j0 - 1, j0);  // cell j0 - 1: flag and denominators only
+  march(j0 - 1, 0);  // cell j0 - 1: flag and denominators only
 
   R amx = R(0), amy = R(0);
   int bad = 0;
@@ -304,20 +331,14 @@ stage2d_strip_kernel(StageArgs a) {
     const int row = jk + wave;  // this wave's row in the x sweep and the update
     const int ux = lane - 1;    // the update's (and x sweep's) column
     const bool owned = lane >= 1 && lane <= TX && i0 + ux < nx && row < j0 + rows;
+    auto fslot = [&](int s) -> int { return (CH * k + s) % (CH + 1); };
+    // the next chunk's rows jk+9 .. jk+12 (one per wave), into the slots of rows jk-4 .. jk-1
+    if (k + 1 < nchunk) stage_row_ahead(jk + 9 + wave);
     // ---- y sweep first: the column march through the chunk's interfaces ----------------------
     // (before the x sweep, so that the x sweep's -dF/dx is not held across the march)
-    if (k > 0) {  // the window is re-read from the ring rather than held across the x sweep
-      z = V(jk - 2);
-      ua = V(jk - 1);
-      ub = V(jk);
-      uc = V(jk + 1);
-      ud = V(jk + 2);
-      ue = V(jk + 3);
-      widen();
-    }
-    if (k == 0) march(j0, jk);  // interface j0 - 1/2 (slot 0)
+    if (k == 0) march(j0, fslot(0));  // interface j0 - 1/2
 #pragma unroll
-    for (int s = 1; s <= CH; ++s) march(jk + s, jk);
+    for (int s = 1; s <= CH; ++s) march(jk + s, fslot(s));
     // ---- x sweep: row `row`, lane l takes cell p = l - 1 and its interface p + 1/2 -----------
     R Lx[M];
     {
@@ -387,15 +408,15 @@ stage2d_strip_kernel(StageArgs a) {
         for (int c = 0; c < M; ++c) s_vm[c][s][lane] = G[c];
       }
     };
-    flux_y(wave + 1);
-    if (k == 0 && wave == 0) flux_y(0);
+    flux_y(fslot(wave + 1));
+    if (k == 0 && wave == 0) flux_y(fslot(0));
     __syncthreads();
     // ---- update of the chunk's cells: row jk + wave, column lane - 1 --------------------------
     if (owned) {
       R unew[M];
 #pragma unroll
       for (int c = 0; c < M; ++c) {
-        const R Gp = s_vm[c][wave + 1][ux], Gm = s_vm[c][wave][ux];
+        const R Gp = s_vm[c][fslot(wave + 1)][ux], Gm = s_vm[c][fslot(wave)][ux];
         R L;
         if constexpr (kExact)
           L = Lx[c] - div_rn(Gp - Gm, dy);
@@ -424,14 +445,18 @@ stage2d_strip_kernel(StageArgs a) {
       }
     }
     if (k + 1 == nchunk) break;
-    __syncthreads();  // the chunk's ring rows and flux slots are read
-    // the top flux becomes the next chunk's bottom one; rows jk+9 .. jk+12 replace jk-3 .. jk
-    if (wave == 0 && lane < TX) {
-#pragma unroll
-      for (int c = 0; c < M; ++c) s_vm[c][0][lane] = s_vm[c][CH][lane];
-    }
-    stage_row(jk + 9 + wave);
-    __syncthreads();
+    // the next chunk's window (rows jk+2 .. jk+7), re-read here rather than held across the x
+    // sweep, and before the barrier: the loads issued above overwrite rows jk .. jk+3's
+    // predecessors, which nothing reads after it
+    z = V(jk + 2);
+    ua = V(jk + 3);
+    ub = V(jk + 4);
+    uc = V(jk + 5);
+    ud = V(jk + 6);
+    ue = V(jk + 7);
+    widen();
+    __builtin_amdgcn_s_waitcnt(0);  // the next chunk's rows are in LDS
+    __syncthreads();                // and this chunk's ring rows and flux slots are read
   }
   if (stage == 0) return;
   // ---- epilogue: alpha of the new state over the strip, and validity ------------------------
