@@ -48,8 +48,8 @@ ACCESSES_PER_CELL_STAGE = 8.0 / 3.0
 METRIC = "cell-updates/s per RK stage at stated L1 err vs FP64 oracle; p50/p99 solve latency"
 
 
-KERNEL_SOURCES = ("npw_device.h", "npw_internal.h", "npw_kernels.h", "npw_kernels2d.h", "npw_kernels_f32.hip",
-                  "npw_kernels_f64.hip")
+KERNEL_SOURCES = ("npw_device.h", "npw_internal.h", "npw_kernels.h", "npw_kernels2d.h", "npw_kernels2d_strip.h",
+                  "npw_kernels_f32.hip", "npw_kernels_f64.hip")
 
 # reconstruction codes of include/npweno.h by name
 RECONS = {"rbf_weno5": 0, "weno5_js": 1, "rbf_eno3": 2, "eno3": 3, "rbf_weno3": 4, "weno3_js": 5, "rbf_eno2": 6,
@@ -66,6 +66,8 @@ def kernel_label(w, prec, shape, batched=False):
     if w.dim == 1:
         lab = f"stage1d_kernel<{R}, {FLUX_NAMES[w.flux]}, {w.ncomp}, {shape['block']}{extra}>"
         return lab + " (batched)" if batched else lab
+    if shape["tile_y"] > 8:  # a column strip walked 4 rows at a time
+        return f"stage2d_strip_kernel<{R}, {FLUX_NAMES[w.flux]}, {w.ncomp}, {shape['tile_x']}, {shape['tile_y']}>"
     share = "" if shape["lds_shared"] else ", recompute"
     return f"stage2d_kernel<{R}, {FLUX_NAMES[w.flux]}, {w.ncomp}, {shape['tile_x']}, {shape['tile_y']}{share}{extra}>"
 

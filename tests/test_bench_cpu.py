@@ -137,3 +137,14 @@ def test_smooth_mask_excludes_the_neighbourhood_of_jumps():
     assert not m[15:25].any() and m[:15].all() and m[25:].all()
     two = np.stack([u, np.ones(n)])
     assert np.array_equal(bench.smooth_mask(two.reshape(-1), 2, (n,)), m)
+
+
+def test_kernel_label_names_the_strip_and_tile_kernels():
+    import types
+
+    import bench
+    w = types.SimpleNamespace(dim=2, flux=2, ncomp=4, recon=0, variables=0)
+    strip = {"block": 256, "tile_x": 62, "tile_y": 16, "lds_shared": 0}
+    tile = {"block": 256, "tile_x": 62, "tile_y": 8, "lds_shared": 0}
+    assert bench.kernel_label(w, 1, strip) == "stage2d_strip_kernel<float, Euler, 4, 62, 16>"
+    assert bench.kernel_label(w, 1, tile) == "stage2d_kernel<float, Euler, 4, 62, 8, recompute>"
