@@ -464,7 +464,8 @@ def error_at_T(w, u_T, prec):
     smooth = np.tile(smooth_mask(ref, w.ncomp, shape), w.ncomp)
     out = {"vs": "double-bulk GPU path at T (bit-identical to the FP64 oracle in the parity tests)",
            "t": st["t"], "rk_steps": st["nsteps"], "l1": float(d.mean()), "linf": float(d.max()),
-           "l1_rel": float(d.sum() / np.abs(ref).sum())}
+           "l1_rel": float(d.sum() / np.abs(ref).sum()),
+           "values_differing_by_more_than": {t: float((d > float(t)).mean()) for t in ("1e-6", "1e-4", "1e-2", "1e-1")}}
     if smooth.any():
         ds = d[smooth]
         out["away_from_discontinuities"] = {
