@@ -809,6 +809,21 @@ __device__ __forceinline__ R wave_max_nonneg(R v) {
   }
 }
 
+// A value the same in every lane, placed in a scalar register (values loaded through a vector
+// load otherwise occupy a vector register per lane for as long as they live).
+__device__ __forceinline__ int scalar_reg(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ long long scalar_reg(long long v) {
+  const unsigned lo = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)v);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)((unsigned long long)v >> 32));
+  return (long long)(((unsigned long long)hi << 32) | lo);
+}
+__device__ __forceinline__ float scalar_reg(float v) {
+  return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
+}
+__device__ __forceinline__ double scalar_reg(double v) {
+  return __longlong_as_double(scalar_reg((long long)__double_as_longlong(v)));
+}
+
 // Workgroups go to the 8 XCDs round robin (dispatch index b to XCD b % 8).  Map dispatch index b
 // of G to a tile so that each XCD owns a contiguous run of tiles (a bijection on [0, G)):
 // neighbouring tiles read each other's edge cells, and within a run they share one L2.

@@ -24,17 +24,6 @@
 
 namespace npw {
 
-// A value the same in every lane, placed in a scalar register.
-__device__ __forceinline__ float scalar_reg(float v) {
-  return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
-}
-__device__ __forceinline__ double scalar_reg(double v) {
-  const long long b = __double_as_longlong(v);
-  const unsigned lo = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)b);
-  const unsigned hi = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)(b >> 32));
-  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
-}
-
 constexpr int kStripTX = 62;  // owned columns of a strip (cells -1..62 of a row fill one wave)
 constexpr int kStripCH = 4;   // rows per chunk (one per wave in the x sweep and the update)
 
@@ -136,12 +125,22 @@ stage2d_strip_kernel(StageArgs a) {
   const int slot_in = stage == 0 ? 0 : stage - 1;
   const unsigned long long spx = sp ? spread_entry(sp, slot_in, 0) : 0ull;
   const unsigned long long spy = sp ? spread_entry(sp, slot_in, 1) : 0ull;
+  // every field of the instance record the stage needs, read before the first branch and store
+  // (later loads would each add a round trip to memory)
   const int err = I->err;
   const Ctl c0 = I->ctl[0], c1 = I->ctl[1], c2 = I->ctl[2];
+  const long long seq_base = scalar_reg(I->seq_base);
+  const double T = scalar_reg(I->T), tol = scalar_reg(I->tol);
+  const double dt_fixed = scalar_reg(I->dt_fixed), cfl = scalar_reg(I->cfl), dxd = scalar_reg(I->dx),
+               dyd = scalar_reg(I->dy);
+  const int i_recon = scalar_reg(I->recon), i_sw = scalar_reg(I->sw);
+  const double i_eps_m = scalar_reg(I->eps_m), i_eps = scalar_reg(I->eps_weno), i_speed_x = scalar_reg(I->speed_x),
+               i_speed_y = scalar_reg(I->speed_y), i_gamma = scalar_reg(I->gamma), i_inv_dx = scalar_reg(I->inv_dx),
+               i_inv_dy = scalar_reg(I->inv_dy);
   unsigned long long ax_bits, ay_bits;
   if (sp) {
     if constexpr (kTag) {
-      const long long n_in = (stage <= 1 ? c0.n : (stage == 2 ? c1.n : c2.n)) - I->seq_base;
+      const long long n_in = (stage <= 1 ? c0.n : (stage == 2 ? c1.n : c2.n)) - seq_base;
       ax_bits = spread_reduce_tagged(spx, 3 * n_in + slot_in);
       ay_bits = spread_reduce_tagged(spy, 3 * n_in + slot_in);
     } else {
@@ -152,8 +151,6 @@ stage2d_strip_kernel(StageArgs a) {
     ax_bits = I->alpha[slot_in][0];
     ay_bits = I->alpha[slot_in][1];
   }
-  const double T = I->T, tol = I->tol;
-  const double dt_fixed = I->dt_fixed, cfl = I->cfl, dxd = I->dx, dyd = I->dy;
   auto zero_slot = [&](int slot) {
     if (sp) {
       if (!kTag && first_block && tid < kSpread) {
@@ -214,13 +211,13 @@ stage2d_strip_kernel(StageArgs a) {
   // they would otherwise sit in a dozen vector registers for the whole chunk loop.
   const R alpha_x = scalar_reg(R(bits_to_double(ax_bits))), alpha_y = scalar_reg(R(bits_to_double(ay_bits)));
   const R rdt = scalar_reg(R(dt));
-  const ReconMode rm = recon_mode(I->recon, I->sw);
+  const ReconMode rm = recon_mode(i_recon, i_sw);
   const bool eno = rm.eno, use_eta = rm.use_eta, use_switch = rm.use_switch;
-  const double eps_m = scalar_reg(I->eps_m);
-  const R eps = scalar_reg(R(I->eps_weno));
-  const R speed_x = scalar_reg(R(I->speed_x)), speed_y = scalar_reg(R(I->speed_y)), gamma = scalar_reg(R(I->gamma));
+  const double eps_m = scalar_reg(i_eps_m);
+  const R eps = scalar_reg(R(i_eps));
+  const R speed_x = scalar_reg(R(i_speed_x)), speed_y = scalar_reg(R(i_speed_y)), gamma = scalar_reg(R(i_gamma));
   const R dx = scalar_reg(R(dxd)), dy = scalar_reg(R(dyd));
-  const R inv_dx = scalar_reg(R(I->inv_dx)), inv_dy = scalar_reg(R(I->inv_dy));
+  const R inv_dx = scalar_reg(R(i_inv_dx)), inv_dy = scalar_reg(R(i_inv_dy));
 
   // The same for a row that is first read in the next chunk.  Float rows inside the grid go
   // straight from memory to LDS (no registers; the loads complete under the chunk's work and are
@@ -491,9 +488,9 @@ stage2d_strip_kernel(StageArgs a) {
       const int k = (blockIdx.y * gridDim.x + blockIdx.x) % kSpread;
       if (sp && kTag) {
         atomicMax(&sp[((slot * 2 + 0) * kSpread + k) * kSpreadStride],
-                  spread_tag(3 * (n - I->seq_base) + stage, float(bits_to_double(mx))));
+                  spread_tag(3 * (n - seq_base) + stage, float(bits_to_double(mx))));
         atomicMax(&sp[((slot * 2 + 1) * kSpread + k) * kSpreadStride],
-                  spread_tag(3 * (n - I->seq_base) + stage, float(bits_to_double(my))));
+                  spread_tag(3 * (n - seq_base) + stage, float(bits_to_double(my))));
       } else {
         atomicMax(sp ? &sp[((slot * 2 + 0) * kSpread + k) * kSpreadStride] : &I->alpha[slot][0], mx);
         atomicMax(sp ? &sp[((slot * 2 + 1) * kSpread + k) * kSpreadStride] : &I->alpha[slot][1], my);
