@@ -140,22 +140,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(
   const int slot_in = stage == 0 ? 0 : stage - 1;
   const unsigned long long spx = sp ? spread_entry(sp, slot_in, 0) : 0ull;
   const unsigned long long spy = sp ? spread_entry(sp, slot_in, 1) : 0ull;
-  // every field of the instance record the stage needs, read before the first branch and store
-  // (later loads would each add a round trip to memory)
   const int err = I->err;
   const Ctl c0 = I->ctl[0], c1 = I->ctl[1], c2 = I->ctl[2];
-  const long long seq_base = scalar_reg(I->seq_base);
-  const double T = scalar_reg(I->T), tol = scalar_reg(I->tol);
-  const double dt_fixed = scalar_reg(I->dt_fixed), cfl = scalar_reg(I->cfl), dxd = scalar_reg(I->dx),
-               dyd = scalar_reg(I->dy);
-  const int i_recon = scalar_reg(I->recon), i_sw = scalar_reg(I->sw);
-  const double i_eps_m = scalar_reg(I->eps_m), i_eps = scalar_reg(I->eps_weno), i_speed_x = scalar_reg(I->speed_x),
-               i_speed_y = scalar_reg(I->speed_y), i_gamma = scalar_reg(I->gamma), i_inv_dx = scalar_reg(I->inv_dx),
-               i_inv_dy = scalar_reg(I->inv_dy);
   unsigned long long ax_bits, ay_bits;
   if (sp) {
     if constexpr (kTag) {
-      const long long n_in = (stage <= 1 ? c0.n : (stage == 2 ? c1.n : c2.n)) - seq_base;
+      const long long n_in = (stage <= 1 ? c0.n : (stage == 2 ? c1.n : c2.n)) - I->seq_base;
       ax_bits = spread_reduce_tagged(spx, 3 * n_in + slot_in);
       ay_bits = spread_reduce_tagged(spy, 3 * n_in + slot_in);
     } else {
@@ -166,6 +156,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(
     ax_bits = I->alpha[slot_in][0];
     ay_bits = I->alpha[slot_in][1];
   }
+  const double T = I->T, tol = I->tol;
+  const double dt_fixed = I->dt_fixed, cfl = I->cfl, dxd = I->dx, dyd = I->dy;
   auto zero_slot = [&](int slot) {
     if (sp) {
       if (!kTag && first_block && tid < kSpread) {
@@ -224,13 +216,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(
   }
   const R alpha_x = R(bits_to_double(ax_bits)), alpha_y = R(bits_to_double(ay_bits));
   const R rdt = R(dt);
-  ReconMode rm = recon_mode(i_recon, i_sw);
+  ReconMode rm = recon_mode(I->recon, I->sw);
   if (!K2) rm.k2 = rm.cross = false;  // launched for a k = 3 instance (Section 6 is k = 2)
   const bool k2 = rm.k2, eno = rm.eno, use_eta = rm.use_eta, use_switch = rm.use_switch, cross = rm.cross;
-  const double eps_m = i_eps_m;
-  const R eps = R(i_eps);
-  const R speed_x = R(i_speed_x), speed_y = R(i_speed_y), gamma = R(i_gamma);
-  const R dx = R(dxd), dy = R(dyd), inv_dx = R(i_inv_dx), inv_dy = R(i_inv_dy);
+  const double eps_m = I->eps_m;
+  const R eps = R(I->eps_weno);
+  const R speed_x = R(I->speed_x), speed_y = R(I->speed_y), gamma = R(I->gamma);
+  const R dx = R(dxd), dy = R(dyd), inv_dx = R(I->inv_dx), inv_dy = R(I->inv_dy);
 
 #pragma unroll
   for (int k = 0; k < NLD; ++k) {
@@ -632,8 +624,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(
     } else {
       const int k = (blockIdx.y * gridDim.x + blockIdx.x) % kSpread;
       if (sp && kTag) {
-        atomicMax(&sp[((slot * 2 + 0) * kSpread + k) * kSpreadStride], spread_tag(3 * (n - seq_base) + stage, float(bits_to_double(mx))));
-        atomicMax(&sp[((slot * 2 + 1) * kSpread + k) * kSpreadStride], spread_tag(3 * (n - seq_base) + stage, float(bits_to_double(my))));
+        atomicMax(&sp[((slot * 2 + 0) * kSpread + k) * kSpreadStride], spread_tag(3 * (n - I->seq_base) + stage, float(bits_to_double(mx))));
+        atomicMax(&sp[((slot * 2 + 1) * kSpread + k) * kSpreadStride], spread_tag(3 * (n - I->seq_base) + stage, float(bits_to_double(my))));
       } else {
         atomicMax(sp ? &sp[((slot * 2 + 0) * kSpread + k) * kSpreadStride] : &I->alpha[slot][0], mx);
         atomicMax(sp ? &sp[((slot * 2 + 1) * kSpread + k) * kSpreadStride] : &I->alpha[slot][1], my);
