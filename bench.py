@@ -355,6 +355,8 @@ def roofline(w, label, cells_per_launch, esize, avg_launch, traffic=None):
               "avg_launch_us": avg_launch * 1e6}
     if w.dim == 2 or w.flux == 2:
         return {"bound": "alu", **{k: alu[k] for k in ("achieved", "peak", "unit", "frac")}, **common,
+                "limiter": "VALU issue: see valu.frac, the issue rate against the ceiling of the kernel's own "
+                           "instruction mix",
                 "flops_per_launch": flops, "peak_basis": "FP32 vector FMA without packed-FP32 instructions",
                 "hbm": hbm}
     return {"bound": "hbm", **{k: hbm[k] for k in ("achieved", "peak", "unit", "frac")}, **common,
