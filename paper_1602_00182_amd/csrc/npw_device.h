@@ -824,6 +824,26 @@ __device__ __forceinline__ double scalar_reg(double v) {
   return __longlong_as_double(scalar_reg((long long)__double_as_longlong(v)));
 }
 
+// Read a value at a workgroup-uniform address through the scalar data cache (a scalar load,
+// counted apart from the vector loads, and fetched once per cache rather than once per wave).
+// The compiler takes memory read this way as unchanging while the kernel runs, so it is only for
+// data that no work item of the running kernel writes before it is read: static fields, and
+// fields that the kernel reads at its start and writes only after its branches on them.
+template <typename T>
+__device__ __forceinline__ T scalar_load(const T* p) {
+  return *(const __attribute__((address_space(4))) T*)p;
+}
+// A tile record read field by field (a whole-struct copy would not become scalar loads).
+__device__ __forceinline__ Tile scalar_load_tile(const Tile* p) {
+  Tile t;
+  t.inst = scalar_load(&p->inst);
+  t.bc = scalar_load(&p->bc);
+  t.start = scalar_load(&p->start);
+  t.nx = scalar_load(&p->nx);
+  t.off = scalar_load(&p->off);
+  return t;
+}
+
 // Workgroups go to the 8 XCDs round robin (dispatch index b to XCD b % 8).  Map dispatch index b
 // of G to a tile so that each XCD owns a contiguous run of tiles (a bijection on [0, G)):
 // neighbouring tiles read each other's edge cells, and within a run they share one L2.
@@ -852,9 +872,12 @@ __device__ __forceinline__ unsigned long long spread_reduce_tagged(unsigned long
 __device__ __forceinline__ unsigned long long spread_reduce(unsigned long long entry) {
   return double_to_bits(wave_max_nonneg(bits_to_double(entry)));
 }
-// This lane's entry of (slot, dir).
+// This lane's entry of (slot, dir), and its address.
+__device__ __forceinline__ const unsigned long long* spread_entry_ptr(const unsigned long long* spread, int slot, int dir) {
+  return &spread[((slot * 2 + dir) * kSpread + (threadIdx.x & (kSpread - 1))) * kSpreadStride];
+}
 __device__ __forceinline__ unsigned long long spread_entry(const unsigned long long* spread, int slot, int dir) {
-  return spread[((slot * 2 + dir) * kSpread + (threadIdx.x & (kSpread - 1))) * kSpreadStride];
+  return *spread_entry_ptr(spread, slot, dir);
 }
 
 

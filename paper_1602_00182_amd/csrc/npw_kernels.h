@@ -75,6 +75,10 @@ __device__ __forceinline__ void stage1d_tile(const StageArgs& a, const Tile tile
   }
 
   // ---- step control (see Ctl): read the word of the previous stage, write our own ---------
+  // The record comes in through scalar loads, so the branches below wait for it alone, and the
+  // staging below waits for the state loads alone.  Every wave of the grid reads the same alpha
+  // lines, so their loads queue behind each other; they are issued after the state loads and
+  // consumed only at the fluxes, with the staging and the reconstructions done meanwhile.
   InstDev* I = a.inst + tile.inst;
   unsigned long long* sp = a.spread;
   const bool lead = (start == 0 && tid == 0);
@@ -82,23 +86,21 @@ __device__ __forceinline__ void stage1d_tile(const StageArgs& a, const Tile tile
   // float bulk: spread entries carry the stage sequence that wrote them (spread_tag)
   constexpr bool kTag = !kExact;
   const int slot_in = stage == 0 ? 0 : stage - 1;
-  const unsigned long long sp_e = sp ? spread_entry(sp, slot_in, 0) : 0ull;
-  const int err = I->err;
-  const Ctl c0 = I->ctl[0], c1 = I->ctl[1], c2 = I->ctl[2];
-  const long long seq_base = I->seq_base;
-  unsigned long long alpha_bits;
-  if (sp) {
-    if constexpr (kTag) {
-      const long long n_in = stage <= 1 ? c0.n : (stage == 2 ? c1.n : c2.n);
-      alpha_bits = spread_reduce_tagged(sp_e, 3 * (n_in - seq_base) + slot_in);
-    } else {
-      alpha_bits = spread_reduce(sp_e);
-    }
-  } else {
-    alpha_bits = I->alpha[slot_in][0];
-  }
-  const double T = I->T, tol = I->tol;
-  const double dt_fixed = I->dt_fixed, cfl = I->cfl, dxd = I->dx;
+  // one vector load on every path (a batch instance reads its own alpha slot), so that the
+  // staging below can wait for the state loads while this one is still in flight
+  const unsigned long long sp_e = *(sp ? spread_entry_ptr(sp, slot_in, 0) : &I->alpha[slot_in][0]);
+  // stage 0 and 1 step from ctl[0], stage 2 from ctl[1], stage 3 from ctl[2]; every branch
+  // below is decided from these loads at once
+  const Ctl* cp = &I->ctl[stage <= 1 ? 0 : stage - 1];
+  const int err = scalar_load(&I->err);
+  const double t = scalar_load(&cp->t), dt_in = scalar_load(&cp->dt);
+  const long long n = scalar_load(&cp->n);
+  const int active_in = scalar_load(&cp->active), home_in = scalar_load(&cp->home);
+  const double T = scalar_load(&I->T), tol = scalar_load(&I->tol);
+  const long long seq_base = scalar_load(&I->seq_base);
+  // a first stage starts a step while the instance has not reached T; the other two go on with
+  // the step that the first one started
+  const bool run = !err && (stage == 0 || (stage == 1 ? (T - t) > tol : active_in != 0));
   // zero an alpha slot before the kernel that accumulates into it runs (tagged slots need not be)
   auto zero_slot = [&](int slot) {
     if (sp) {
@@ -111,61 +113,45 @@ __device__ __forceinline__ void stage1d_tile(const StageArgs& a, const Tile tile
       I->alpha[slot][1] = 0ull;
     }
   };
-  if (err) return;
-  double t, dt = 0.0;
-  long long n;
-  if (stage == 1) {
-    t = c0.t;
-    n = c0.n;
-    const bool active = (T - t) > tol;
-    if (active) dt = step_dt<1>(dt_fixed, cfl, dxd, 0.0, T, t, bits_to_double(alpha_bits), 0.0);
-    if (lead) {
+  if (lead && !err) {
+    if (stage == 1 && !run) {  // the instance is done: an idle step record
       Ctl c;
       c.t = t;
-      c.dt = dt;
+      c.dt = 0.0;
       c.n = n;
-      c.active = active ? 1 : 0;
+      c.active = 0;
       c.home = par;
       I->ctl[1] = c;
-    }
-    if (!active) return;
-    zero_slot(2);
-  } else if (stage == 2) {
-    if (lead) I->ctl[2] = c1;
-    if (!c1.active) return;
-    zero_slot(0);
-    t = c1.t;
-    dt = c1.dt;
-    n = c1.n;
-  } else if (stage == 3) {
-    if (!c2.active) return;
-    if (lead) {
+    } else if (stage == 2) {  // the third stage steps from the same record
+      Ctl c;
+      c.t = t;
+      c.dt = dt_in;
+      c.n = n;
+      c.active = active_in;
+      c.home = home_in;
+      I->ctl[2] = c;
+    } else if (stage == 3 && run) {  // the next step starts from u^(n+1), written by this stage
       Ctl d;
-      d.t = c2.t + c2.dt;
+      d.t = t + dt_in;
       d.dt = 0.0;
-      d.n = c2.n + 1;
+      d.n = n + 1;
       d.active = 0;
       d.home = par ^ 1;
       I->ctl[0] = d;
     }
-    zero_slot(1);
-    t = c2.t;
-    dt = c2.dt;
-    n = c2.n;
-  } else {
-    t = c0.t;
-    n = c0.n;
   }
-  const R alpha = R(bits_to_double(alpha_bits));
-  const R rdt = R(dt);
-  ReconMode rm = recon_mode(I->recon, I->sw);
+  if (!run) return;
+  if (stage != 0) zero_slot(stage == 1 ? 2 : (stage == 2 ? 0 : 1));
+  double dt = stage == 1 ? 0.0 : dt_in;
+  ReconMode rm = recon_mode(scalar_load(&I->recon), scalar_load(&I->sw));
   if (!K2) rm.k2 = false;  // launched for k = 3 instances only
   const bool k2 = rm.k2, eno = rm.eno, use_eta = rm.use_eta, use_switch = rm.use_switch;
-  const double eps_m = I->eps_m;
-  const R eps = R(I->eps_weno);
-  const R speed = R(I->speed_x), gamma = R(I->gamma);
+  const double eps_m = scalar_load(&I->eps_m);
+  const R eps = R(scalar_load(&I->eps_weno));
+  const R speed = R(scalar_load(&I->speed_x)), gamma = R(scalar_load(&I->gamma));
+  const double dxd = scalar_load(&I->dx);
   const R dx = R(dxd);
-  const R inv_dx = R(I->inv_dx);
+  const R inv_dx = R(scalar_load(&I->inv_dx));
 
   // ---- stage input into LDS ----------------------------------------------------------------
 #pragma unroll
@@ -223,8 +209,8 @@ __device__ __forceinline__ void stage1d_tile(const StageArgs& a, const Tile tile
   // ---- interface phase: x_{cell+1/2} between cell start-1+tid and the next (tid < BS-1) ----
   // eta (Table 3 caption) zeroed by the switch, v^- of the left cell, v^+ of the right cell,
   // and the global Lax-Friedrichs flux.
+  R A[M], B[M];
   if (tid < BS - 1) {
-    R A[M], B[M], H[M];
     if constexpr (CHAR) {  // cells i-2..i+3 of interface i+1/2 are LDS tid..tid+5
       R U[6][M];
 #pragma unroll
@@ -263,10 +249,38 @@ __device__ __forceinline__ void stage1d_tile(const StageArgs& a, const Tile tile
                             eta, s_den[c][0][tid + 1], s_den[c][1][tid + 1], s_den[c][2][tid + 1]);
       }
     }
+  }
+  // alpha of the stage input (max over the spread entries: the whole wave takes part), then the
+  // step size of a first stage, which its lead thread records for the two stages that follow
+  unsigned long long alpha_bits;
+  if (sp) {
+    if constexpr (kTag)
+      alpha_bits = spread_reduce_tagged(sp_e, 3 * (n - seq_base) + slot_in);
+    else
+      alpha_bits = spread_reduce(sp_e);
+  } else {
+    alpha_bits = sp_e;
+  }
+  const R alpha = R(bits_to_double(alpha_bits));
+  if (tid < BS - 1) {
+    R H[M];
     lf_flux<R, FLUX, M, 0>(A, B, alpha, speed, gamma, H);
 #pragma unroll
     for (int c = 0; c < M; ++c) s_F[c][tid] = H[c];
   }
+  if (stage == 1) {
+    dt = step_dt<1>(scalar_load(&I->dt_fixed), scalar_load(&I->cfl), dxd, 0.0, T, t, bits_to_double(alpha_bits), 0.0);
+    if (lead) {
+      Ctl c;
+      c.t = t;
+      c.dt = dt;
+      c.n = n;
+      c.active = 1;
+      c.home = par;
+      I->ctl[1] = c;
+    }
+  }
+  const R rdt = R(dt);
   tile_barrier<BS>();
   // ---- update of the owned cells (tid = 1 .. BS-2) ---------------------------------------------
   R amax = R(0);
@@ -344,11 +358,11 @@ __global__ __launch_bounds__(BS) void stage1d_kernel(StageArgs a) {
   }
   const int nt = a.ntiles_dev ? *a.ntiles_dev : a.ntiles;
   if ((int)gridDim.x == nt) {  // one tile per workgroup (a batch): XCD-contiguous runs of the table
-    stage1d_tile<R, FLUX, M, BS, CHAR, K2>(a, a.tiles[xcd_contiguous_tile(blockIdx.x, nt)]);
+    stage1d_tile<R, FLUX, M, BS, CHAR, K2>(a, scalar_load_tile(&a.tiles[xcd_contiguous_tile(blockIdx.x, nt)]));
     return;
   }
   for (int ti = blockIdx.x; ti < nt; ti += gridDim.x) {
-    stage1d_tile<R, FLUX, M, BS, CHAR, K2>(a, a.tiles[ti]);
+    stage1d_tile<R, FLUX, M, BS, CHAR, K2>(a, scalar_load_tile(&a.tiles[ti]));
     __syncthreads();  // LDS is reused by the next tile
   }
 }
