@@ -774,16 +774,19 @@ __device__ __forceinline__ unsigned long long double_to_bits(double d) {
   return (unsigned long long)__double_as_longlong(d);
 }
 
-// Max of a non-negative value over the wavefront with DPP moves (rows of 16 lanes, then the
-// row broadcasts); lanes without a source read 0, the identity for non-negative values.  Every
-// lane gets the result of lane 63.
+// Max of a non-negative value (+0 up to +inf, never NaN or -0) over the wavefront with DPP moves
+// (rows of 16 lanes, then the row broadcasts); lanes without a source read 0, the identity for
+// non-negative values.  Every lane gets the result of lane 63.
 template <int CTRL, int ROWS>
 __device__ __forceinline__ unsigned dpp_take(unsigned v) {
   return (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, ROWS, 0xf, true);
 }
 template <int CTRL, int ROWS>
 __device__ __forceinline__ float dpp_max_step(float v) {
-  return fmaxf(v, __uint_as_float(dpp_take<CTRL, ROWS>(__float_as_uint(v))));
+  // non-negative floats order as their bit patterns: an integer max, which the compiler merges
+  // with the lane move into one instruction
+  const unsigned b = __float_as_uint(v), o = dpp_take<CTRL, ROWS>(b);
+  return __uint_as_float(b > o ? b : o);
 }
 template <int CTRL, int ROWS>
 __device__ __forceinline__ double dpp_max_step(double v) {
@@ -806,6 +809,39 @@ __device__ __forceinline__ R wave_max_nonneg(R v) {
     const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, 63);
     const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), 63);
     return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+  }
+}
+
+// Packed alpha slots (one entry per tile, see StageArgs::pack) are read as 16-byte vectors; the
+// max of a lane's vectors, then over the wave (entries are non-negative; unused ones hold 0).
+template <typename R>
+struct PackVecT;
+template <>
+struct PackVecT<float> {
+  using type = float4;
+};
+template <>
+struct PackVecT<double> {
+  using type = double2;
+};
+template <typename R>
+using PackVec = typename PackVecT<R>::type;
+
+template <typename R, int NL>
+__device__ __forceinline__ R pack_max(const PackVec<R> (&pv)[NL]) {
+  if constexpr (sizeof(R) == 4) {  // as bit patterns, like wave_max_nonneg
+    auto mx = [](unsigned x, unsigned y) { return x > y ? x : y; };
+    unsigned v = 0u;
+#pragma unroll
+    for (int c = 0; c < NL; ++c)
+      v = mx(v, mx(mx(__float_as_uint(pv[c].x), __float_as_uint(pv[c].y)),
+                   mx(__float_as_uint(pv[c].z), __float_as_uint(pv[c].w))));
+    return wave_max_nonneg<float>(__uint_as_float(v));
+  } else {
+    double v = 0.0;
+#pragma unroll
+    for (int c = 0; c < NL; ++c) v = fmax(v, fmax(pv[c].x, pv[c].y));
+    return wave_max_nonneg<double>(v);
   }
 }
 

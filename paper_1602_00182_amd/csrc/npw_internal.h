@@ -76,6 +76,11 @@ struct StageArgs {
   // spread[((slot * 2 + dir) * kSpread + k) * kSpreadStride].  Null for batches (they use
   // InstDev.alpha directly, with few workgroups per instance).
   unsigned long long* spread;
+  // A 1D single grid of at most kPackMax tiles launched with 64 or 128 threads per workgroup
+  // keeps one entry per tile instead (alpha in the bulk precision, entry (slot, tile) at
+  // pack[slot * kPackMax + tile]): a plain store per workgroup and kPackLoads vector loads per
+  // lane replace the atomic max and its spread entry.  Null otherwise.
+  void* pack = nullptr;
 };
 
 constexpr int kSpread = 64;
@@ -83,6 +88,16 @@ constexpr int kSpreadStride = 16;  // 128 bytes between entries
 static_assert(kSpread >= 1 && kSpread <= 64 && (kSpread & (kSpread - 1)) == 0,
               "a wave reads one spread entry per lane (lane & (kSpread - 1))");
 constexpr int kSpreadWords = 3 * 2 * kSpread * kSpreadStride;
+// Packed slots hold up to 1280 tiles: the 1058 of a 65536-cell grid at 64 threads per workgroup,
+// with room, read in 5 float (10 double) 16-byte loads per lane.  Every load costs the
+// latency-bound stage time whether or not its entries are in use (3 unused loads of 8 measured
+// 0.07 us of a 3.2 us stage), so the size stays near the grids that need it; larger grids are
+// not latency-bound and use the spread entries.
+constexpr int kPackMax = 1280;
+constexpr int kPackWords = 3 * kPackMax;  // 64-bit words: three slots of double entries
+template <typename R>
+constexpr int kPackLoads = kPackMax * (int)sizeof(R) / (64 * 16);  // 16-byte loads per lane
+static_assert(kPackMax * 4 % (64 * 16) == 0, "whole 16-byte loads per lane in either precision");
 
 // Launchers implemented in the kernel translation units (one per bulk precision).
 hipError_t launch_stage_f64(int flux, int ncomp, int block, const StageArgs& a, hipStream_t s);
@@ -99,13 +114,13 @@ constexpr int k2dShapes = 9;
 constexpr int k2dStripFirst = 6;
 hipError_t launch_stage2d_f64(int flux, int ncomp, int shape, const StageArgs& a, hipStream_t s);
 hipError_t launch_stage2d_f32(int flux, int ncomp, int shape, const StageArgs& a, hipStream_t s);
-// State check of u^n for ninst instances: alpha slot 0 (and the spread entries of a single grid),
-// finiteness/physicality and the per-component FP64 sums.  scratch holds G * ninst partial
-// records (kCheckPartialBytes each); G workgroups per instance.
+// State check of u^n for ninst instances: alpha slot 0 (and the spread entries and packed slots
+// of a single grid, either may be null), finiteness/physicality and the per-component FP64 sums.
+// scratch holds G * ninst partial records (kCheckPartialBytes each); G workgroups per instance.
 constexpr int kCheckPartialBytes = 56;
 hipError_t launch_init_f64(int flux, int ncomp, InstDev* inst, int ninst, void* P0, void* P1,
-                           unsigned long long* spread, void* scratch, int G, hipStream_t s);
+                           unsigned long long* spread, void* pack, void* scratch, int G, hipStream_t s);
 hipError_t launch_init_f32(int flux, int ncomp, InstDev* inst, int ninst, void* P0, void* P1,
-                           unsigned long long* spread, void* scratch, int G, hipStream_t s);
+                           unsigned long long* spread, void* pack, void* scratch, int G, hipStream_t s);
 
 }  // namespace npw

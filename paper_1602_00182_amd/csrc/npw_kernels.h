@@ -31,7 +31,8 @@ __device__ __forceinline__ void tile_barrier() {
     __syncthreads();
 }
 
-template <typename R, int FLUX, int M, int BS, bool CHAR, bool K2>
+// PACK: a single grid whose alpha slots hold one entry per tile (StageArgs::pack).
+template <typename R, int FLUX, int M, int BS, bool CHAR, bool K2, bool PACK>
 __device__ __forceinline__ void stage1d_tile(const StageArgs& a, const Tile tile) {
   constexpr bool kExact = std::is_same<R, double>::value;
   constexpr int W = BS + 4;  // LDS cells per component: start-3 .. start+BS
@@ -86,9 +87,24 @@ __device__ __forceinline__ void stage1d_tile(const StageArgs& a, const Tile tile
   // float bulk: spread entries carry the stage sequence that wrote them (spread_tag)
   constexpr bool kTag = !kExact;
   const int slot_in = stage == 0 ? 0 : stage - 1;
-  // one vector load on every path (a batch instance reads its own alpha slot), so that the
-  // staging below can wait for the state loads while this one is still in flight
-  const unsigned long long sp_e = *(sp ? spread_entry_ptr(sp, slot_in, 0) : &I->alpha[slot_in][0]);
+  // Alpha of the stage input: every entry of a packed slot (kPackLoads 16-byte loads per lane;
+  // loads past the grid's tiles re-read the lane's first vector), else one spread entry per lane,
+  // else (a batch instance) its own slot.  The same loads on every path, so that the staging below
+  // can wait for the state loads while these are still in flight.
+  PackVec<R> pv[PACK ? kPackLoads<R> : 1];
+  unsigned long long sp_e = 0ull;
+  if constexpr (PACK) {
+    constexpr int kPer = 16 / (int)sizeof(R);  // entries per vector
+    const PackVec<R>* P = reinterpret_cast<const PackVec<R>*>(static_cast<const R*>(a.pack) + slot_in * kPackMax);
+    const int G = (int)gridDim.x, lane = tid & 63;
+#pragma unroll
+    for (int c = 0; c < kPackLoads<R>; ++c) {
+      const int q = c * 64 + lane;
+      pv[c] = P[q * kPer < G ? q : lane];
+    }
+  } else {
+    sp_e = *(sp ? spread_entry_ptr(sp, slot_in, 0) : &I->alpha[slot_in][0]);
+  }
   // stage 0 and 1 step from ctl[0], stage 2 from ctl[1], stage 3 from ctl[2]; every branch
   // below is decided from these loads at once
   const Ctl* cp = &I->ctl[stage <= 1 ? 0 : stage - 1];
@@ -253,7 +269,9 @@ __device__ __forceinline__ void stage1d_tile(const StageArgs& a, const Tile tile
   // alpha of the stage input (max over the spread entries: the whole wave takes part), then the
   // step size of a first stage, which its lead thread records for the two stages that follow
   unsigned long long alpha_bits;
-  if (sp) {
+  if constexpr (PACK) {
+    alpha_bits = double_to_bits(double(pack_max<R, kPackLoads<R>>(pv)));
+  } else if (sp) {
     if constexpr (kTag)
       alpha_bits = spread_reduce_tagged(sp_e, 3 * (n - seq_base) + slot_in);
     else
@@ -323,7 +341,6 @@ __device__ __forceinline__ void stage1d_tile(const StageArgs& a, const Tile tile
         w = s_bad[k] > w ? s_bad[k] : w;
       }
     }
-    const int slot = stage == 1 ? 1 : (stage == 2 ? 2 : 0);
     if (w) {
       const int code = w == 2 ? NPW_ENONPHYSICAL : NPW_ENONFINITE;
       if (atomicCAS(&I->err, 0, code) == 0) {
@@ -333,36 +350,41 @@ __device__ __forceinline__ void stage1d_tile(const StageArgs& a, const Tile tile
         I->err_home = par;
       }
     } else {
-      if (sp && kTag)
-        atomicMax(&sp[((slot * 2 + 0) * kSpread + blockIdx.x % kSpread) * kSpreadStride],
-                  spread_tag(3 * (n - seq_base) + stage, float(bits_to_double(m))));
-      else
-        atomicMax(sp ? &sp[((slot * 2 + 0) * kSpread + blockIdx.x % kSpread) * kSpreadStride] : &I->alpha[slot][0], m);
+      const int slot_out = stage == 1 ? 1 : (stage == 2 ? 2 : 0);
+      if constexpr (PACK) {  // this tile's entry: a plain store, no other workgroup writes it
+        static_cast<R*>(a.pack)[slot_out * kPackMax + xcd_contiguous_tile(blockIdx.x, gridDim.x)] =
+            R(bits_to_double(m));
+      } else {
+        unsigned long long* const aout =
+            sp ? &sp[((slot_out * 2 + 0) * kSpread + blockIdx.x % kSpread) * kSpreadStride] : &I->alpha[slot_out][0];
+        atomicMax(aout, (sp && kTag) ? spread_tag(3 * (n - seq_base) + stage, float(bits_to_double(m))) : m);
+      }
     }
   }
 }
 
 // Grid-stride loop over the tile table; the tile count is read from device memory when the
 // table is shared with a serving loop, so captured graphs stay valid as instances come and go.
-template <typename R, int FLUX, int M, int BS, bool CHAR = false, bool K2 = true>
+// PACK: single grids with packed alpha slots only.
+template <typename R, int FLUX, int M, int BS, bool CHAR = false, bool K2 = true, bool PACK = false>
 __global__ __launch_bounds__(BS) void stage1d_kernel(StageArgs a) {
-  if (a.tiles == nullptr) {  // single instance: tiles follow from the block index
+  if (PACK || a.tiles == nullptr) {  // single instance: tiles follow from the block index
     Tile t;
     t.inst = 0;
     t.bc = a.bc;
     t.start = xcd_contiguous_tile(blockIdx.x, gridDim.x) * (BS - 2);
     t.nx = a.nx;
     t.off = 0;
-    stage1d_tile<R, FLUX, M, BS, CHAR, K2>(a, t);
+    stage1d_tile<R, FLUX, M, BS, CHAR, K2, PACK>(a, t);
     return;
   }
   const int nt = a.ntiles_dev ? *a.ntiles_dev : a.ntiles;
   if ((int)gridDim.x == nt) {  // one tile per workgroup (a batch): XCD-contiguous runs of the table
-    stage1d_tile<R, FLUX, M, BS, CHAR, K2>(a, scalar_load_tile(&a.tiles[xcd_contiguous_tile(blockIdx.x, nt)]));
+    stage1d_tile<R, FLUX, M, BS, CHAR, K2, false>(a, scalar_load_tile(&a.tiles[xcd_contiguous_tile(blockIdx.x, nt)]));
     return;
   }
   for (int ti = blockIdx.x; ti < nt; ti += gridDim.x) {
-    stage1d_tile<R, FLUX, M, BS, CHAR, K2>(a, scalar_load_tile(&a.tiles[ti]));
+    stage1d_tile<R, FLUX, M, BS, CHAR, K2, false>(a, scalar_load_tile(&a.tiles[ti]));
     __syncthreads();  // LDS is reused by the next tile
   }
 }
@@ -442,11 +464,19 @@ __global__ __launch_bounds__(256) void check_partial_kernel(InstDev* inst, void*
   }
 }
 
+// R: the bulk precision (the type of packed alpha entries).
+template <typename R>
 static __global__ __launch_bounds__(64) void check_final_kernel(InstDev* inst, int ninst, const CheckPartial* part, int G,
-                                                                int ncomp, unsigned long long* spread, int tagged) {
+                                                                int ncomp, unsigned long long* spread, R* pack,
+                                                                int tagged) {
   const int b = blockIdx.x * 64 + threadIdx.x;
-  if (spread && blockIdx.x == 0) {  // single grid: entry 0 of slot 0 holds alpha, every other entry starts at 0
+  // single grid: entry 0 of slot 0 holds alpha, every other entry (all packed slots included)
+  // starts at 0
+  if (spread && blockIdx.x == 0) {
     for (int k = threadIdx.x; k < 3 * 2 * kSpread; k += 64) spread[k * kSpreadStride] = 0ull;
+  }
+  if (pack && blockIdx.x == 0) {
+    for (int k = threadIdx.x; k < 3 * kPackMax; k += 64) pack[k] = R(0);
   }
   __syncthreads();
   if (b >= ninst) return;
@@ -465,6 +495,7 @@ static __global__ __launch_bounds__(64) void check_final_kernel(InstDev* inst, i
   for (int c = 0; c < 4; ++c) I->mass[c] = c < ncomp ? tot[c] * area : 0.0;
   I->alpha[0][0] = mx;
   I->alpha[0][1] = my;
+  if (pack) pack[0] = R(bits_to_double(mx));
   if (spread) {  // the state of step n opens sequence 3 (n - seq_base) (see spread_tag)
     const long long seq = 3 * (I->ctl[0].n - I->seq_base);
     spread[(0 * kSpread + 0) * kSpreadStride] = tagged ? spread_tag(seq, float(bits_to_double(mx))) : mx;

@@ -5,26 +5,38 @@
 
 namespace npw {
 
-template <int BS, bool K2>
+template <int BS, bool K2, bool PACK>
 static hipError_t launch_stage_k(int flux, int ncomp, const StageArgs& a, hipStream_t s) {
   const dim3 grid(a.ntiles), block(BS);
   if (flux == kAdvection && ncomp == 1)
-    stage1d_kernel<float, kAdvection, 1, BS, false, K2><<<grid, block, 0, s>>>(a);
+    stage1d_kernel<float, kAdvection, 1, BS, false, K2, PACK><<<grid, block, 0, s>>>(a);
   else if (flux == kBurgers && ncomp == 1)
-    stage1d_kernel<float, kBurgers, 1, BS, false, K2><<<grid, block, 0, s>>>(a);
+    stage1d_kernel<float, kBurgers, 1, BS, false, K2, PACK><<<grid, block, 0, s>>>(a);
   else if (flux == kEuler && ncomp == 3 && a.charw)
-    stage1d_kernel<float, kEuler, 3, BS, true, K2><<<grid, block, 0, s>>>(a);
+    stage1d_kernel<float, kEuler, 3, BS, true, K2, PACK><<<grid, block, 0, s>>>(a);
   else if (flux == kEuler && ncomp == 3)
-    stage1d_kernel<float, kEuler, 3, BS, false, K2><<<grid, block, 0, s>>>(a);
+    stage1d_kernel<float, kEuler, 3, BS, false, K2, PACK><<<grid, block, 0, s>>>(a);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();
 }
 
+// Packed alpha slots (a.pack) exist for 64- and 128-thread workgroups only, and for at most
+// kPackMax tiles.
 template <int BS>
 static hipError_t launch_stage_bs(int flux, int ncomp, const StageArgs& a, hipStream_t s) {
   if (a.ntiles <= 0) return hipSuccess;
-  return a.any_k2 ? launch_stage_k<BS, true>(flux, ncomp, a, s) : launch_stage_k<BS, false>(flux, ncomp, a, s);
+  if constexpr (BS <= 128) {
+    if (a.pack) {
+      if (a.tiles != nullptr || a.ntiles > kPackMax) return hipErrorInvalidValue;
+      return a.any_k2 ? launch_stage_k<BS, true, true>(flux, ncomp, a, s)
+                      : launch_stage_k<BS, false, true>(flux, ncomp, a, s);
+    }
+  } else {
+    if (a.pack) return hipErrorInvalidValue;
+  }
+  return a.any_k2 ? launch_stage_k<BS, true, false>(flux, ncomp, a, s)
+                  : launch_stage_k<BS, false, false>(flux, ncomp, a, s);
 }
 
 hipError_t launch_stage_f32(int flux, int ncomp, int block, const StageArgs& a, hipStream_t s) {
@@ -87,7 +99,7 @@ hipError_t launch_stage2d_f32(int flux, int ncomp, int shape, const StageArgs& a
 }
 
 hipError_t launch_init_f32(int flux, int ncomp, InstDev* inst, int ninst, void* P0, void* P1,
-                           unsigned long long* spread, void* scratch, int G, hipStream_t s) {
+                           unsigned long long* spread, void* pack, void* scratch, int G, hipStream_t s) {
   if (ninst <= 0) return hipSuccess;
   CheckPartial* part = reinterpret_cast<CheckPartial*>(scratch);
   const dim3 grid(G, ninst), block(256);
@@ -103,7 +115,8 @@ hipError_t launch_init_f32(int flux, int ncomp, InstDev* inst, int ninst, void* 
     return hipErrorInvalidValue;
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  check_final_kernel<<<(ninst + 63) / 64, 64, 0, s>>>(inst, ninst, part, G, ncomp, spread, 1);
+  check_final_kernel<float><<<(ninst + 63) / 64, 64, 0, s>>>(inst, ninst, part, G, ncomp, spread,
+                                                           static_cast<float*>(pack), 1);
   return hipGetLastError();
 }
 

@@ -48,6 +48,7 @@ struct npw_solver {
   void* C = nullptr;
   void* scratch = nullptr;      // rhs destination when the caller passes host memory
   unsigned long long* spread = nullptr;  // spread alpha slots (single-grid solvers)
+  void* pack = nullptr;                   // packed alpha slots (1D single grids), after the spread
   void* check_part = nullptr;   // partial records of the state check
   int check_G = 1;              // workgroups per instance in the state check
   std::map<int, hipGraphExec_t> graphs;  // (steps per graph, start parity) -> executable graph
@@ -131,10 +132,15 @@ hipError_t launch_stage(const npw_solver* s, const StageArgs& a, hipStream_t st)
 
 hipError_t launch_init(const npw_solver* s, hipStream_t st) {
   return s->precision == NPW_FP64 ? npw::launch_init_f64(s->flux, s->ncomp, s->d_inst, s->ninst, s->P0, s->P1,
-                                                         s->spread, s->check_part, s->check_G, st)
+                                                         s->spread, s->pack, s->check_part, s->check_G, st)
                                   : npw::launch_init_f32(s->flux, s->ncomp, s->d_inst, s->ninst, s->P0, s->P1,
-                                                         s->spread, s->check_part, s->check_G, st);
+                                                         s->spread, s->pack, s->check_part, s->check_G, st);
 }
+
+// A 1D single grid launched with at most 128 threads per workgroup over at most kPackMax tiles
+// exchanges alpha through its packed slots (see StageArgs::pack); the block size and so the tile
+// count are fixed between state checks, which clear those slots.
+bool use_pack(const npw_solver* s) { return s->pack != nullptr && s->block <= 128 && s->ntiles <= npw::kPackMax; }
 
 StageArgs stage_args(const npw_solver* s, int stage, int par, void* out) {
   StageArgs a;
@@ -154,6 +160,7 @@ StageArgs stage_args(const npw_solver* s, int stage, int par, void* out) {
   a.charw = s->charw;
   a.any_k2 = s->any_k2;
   a.spread = s->spread;
+  a.pack = use_pack(s) ? s->pack : nullptr;
   return a;
 }
 
@@ -677,11 +684,13 @@ static int create_common(const npw_params* p, int32_t count, const void* const* 
       hipMalloc(&s->C, bytes) != hipSuccess || hipMalloc(&s->d_inst, sizeof(InstDev) * count) != hipSuccess ||
       hipMalloc(&s->d_tiles, sizeof(Tile) * max_tiles(s)) != hipSuccess ||
       hipHostMalloc(&s->h_pin, sizeof(InstDev) * count, hipHostMallocDefault) != hipSuccess ||
-      (!batch && hipMalloc(&s->spread, sizeof(unsigned long long) * npw::kSpreadWords) != hipSuccess) ||
+      (!batch && hipMalloc(&s->spread, sizeof(unsigned long long) * (npw::kSpreadWords + npw::kPackWords)) !=
+                     hipSuccess) ||
       hipMalloc(&s->check_part, (size_t)npw::kCheckPartialBytes * s->check_G * count) != hipSuccess) {
     release(s);
     return NPW_ENOMEM;
   }
+  if (s->spread && s->dim == 1) s->pack = s->spread + npw::kSpreadWords;
   if (enter(s) || hipMemcpyAsync(s->d_tiles, s->tiles_all.data(), sizeof(Tile) * s->tiles_all.size(),
                                  hipMemcpyHostToDevice, s->stream) != hipSuccess) {
     release(s);
@@ -1032,8 +1041,8 @@ int rhs_noalloc_impl(const npw_params* p, const void* u, void* L_out, void* hip_
   HIP_TRY(hipGetLastError());
   void* uu = const_cast<void*>(u);  // read only: rhs mode loads the state and writes L_out
   const int flux = p->flux, m = p->ncomp;
-  HIP_TRY(p->precision == NPW_FP64 ? npw::launch_init_f64(flux, m, rec, 1, uu, uu, spread, part, G, st)
-                                   : npw::launch_init_f32(flux, m, rec, 1, uu, uu, spread, part, G, st));
+  HIP_TRY(p->precision == NPW_FP64 ? npw::launch_init_f64(flux, m, rec, 1, uu, uu, spread, nullptr, part, G, st)
+                                   : npw::launch_init_f32(flux, m, rec, 1, uu, uu, spread, nullptr, part, G, st));
   StageArgs a;
   std::memset(&a, 0, sizeof a);
   a.inst = rec;
@@ -1050,6 +1059,7 @@ int rhs_noalloc_impl(const npw_params* p, const void* u, void* L_out, void* hip_
   a.charw = p->variables == NPW_CHARACTERISTIC ? 1 : 0;
   a.any_k2 = p->recon >= NPW_RBF_WENO3 ? 1 : 0;
   a.spread = spread;
+  a.pack = nullptr;  // the spread entries: the scratch array holds no packed slots
   if (p->dim == 1) {
     const int block = env_block();
     a.ntiles = (int)((p->nx + block - 3) / (block - 2));

@@ -156,9 +156,9 @@ int pool_of(const npw_params* p) {  // advection 0, Burgers 1, Euler 2, Euler ch
 // stream.  Checks on one stream run in order, so they share the pool's partial records.
 hipError_t launch_check(const npw_server* s, const Pool& pl, int slot, long long cells) {
   return s->precision == NPW_FP64
-             ? npw::launch_init_f64(pl.flux, pl.ncomp, pl.d_inst + slot, 1, s->P0, s->P1, nullptr, pl.d_check,
+             ? npw::launch_init_f64(pl.flux, pl.ncomp, pl.d_inst + slot, 1, s->P0, s->P1, nullptr, nullptr, pl.d_check,
                                     check_groups(cells), pl.stream)
-             : npw::launch_init_f32(pl.flux, pl.ncomp, pl.d_inst + slot, 1, s->P0, s->P1, nullptr, pl.d_check,
+             : npw::launch_init_f32(pl.flux, pl.ncomp, pl.d_inst + slot, 1, s->P0, s->P1, nullptr, nullptr, pl.d_check,
                                     check_groups(cells), pl.stream);
 }
 
