@@ -61,11 +61,13 @@ __device__ __forceinline__ void stage1d_tile(const StageArgs& a, const Tile tile
   const bool owned = (tid >= 1 && tid <= BS - 2 && cell < nx);
   R ld0[M], ld1[M], upt[M];
   {
-    const int g0 = ghost_index(start - 3 + tid, nx, bc);
+    // the window start-3 .. start+BS lies inside the grid for every tile but the first and last
+    const bool inner = start >= 3 && start + BS < nx;
+    const int g0 = inner ? start - 3 + tid : ghost_index(start - 3 + tid, nx, bc);
 #pragma unroll
     for (int c = 0; c < M; ++c) ld0[c] = src[c * nx + g0];
     if (tid < W - BS) {
-      const int g1 = ghost_index(start - 3 + BS + tid, nx, bc);
+      const int g1 = inner ? start - 3 + BS + tid : ghost_index(start - 3 + BS + tid, nx, bc);
 #pragma unroll
       for (int c = 0; c < M; ++c) ld1[c] = src[c * nx + g1];
     }
