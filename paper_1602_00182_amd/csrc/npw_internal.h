@@ -81,7 +81,13 @@ struct StageArgs {
   // pack[slot * kPackMax + tile]): a plain store per workgroup and kPackLoads vector loads per
   // lane replace the atomic max and its spread entry.  Null otherwise.
   void* pack = nullptr;
+  // The reconstruction of every instance of the launch when it is the one a kernel can be built
+  // for alone (kSchemeRbfWeno5Switch: RBF-WENO5 with the Section 4 switch), else kSchemeAny (the
+  // kernel reads it from the instance record).
+  int scheme = 0;
 };
+constexpr int kSchemeAny = 0;
+constexpr int kSchemeRbfWeno5Switch = 1;
 
 constexpr int kSpread = 64;
 constexpr int kSpreadStride = 16;  // 128 bytes between entries

@@ -31,7 +31,10 @@ __device__ __forceinline__ void tile_barrier() {
     __syncthreads();
 }
 
-// PACK: a single grid whose alpha slots hold one entry per tile (StageArgs::pack).
+// PACK: a single grid whose alpha slots hold one entry per tile (StageArgs::pack).  (A kernel
+// built for one reconstruction alone was 5 % faster on a single grid, but it rounded some float
+// results differently from this one, which batches, serving pools and the allocation-free
+// right-hand side run, and those promise a single grid's results bit for bit.)
 template <typename R, int FLUX, int M, int BS, bool CHAR, bool K2, bool PACK>
 __device__ __forceinline__ void stage1d_tile(const StageArgs& a, const Tile tile) {
   constexpr bool kExact = std::is_same<R, double>::value;

@@ -79,7 +79,10 @@ template <int H>
 static hipError_t launch2d_strip(int flux, int ncomp, const StageArgs& a, hipStream_t s) {
   if (flux != kEuler || ncomp != 4 || a.charw || a.any_k2) return launch2d<62, 8, false>(flux, ncomp, a, s);
   const dim3 grid((unsigned)((a.nx + kStripTX - 1) / kStripTX), (unsigned)((a.ny + H - 1) / H)), block(256);
-  stage2d_strip_kernel<double, kEuler, H><<<grid, block, 0, s>>>(a);
+  if (a.scheme == kSchemeRbfWeno5Switch)
+    stage2d_strip_kernel<double, kEuler, H, kSchemeRbfWeno5Switch><<<grid, block, 0, s>>>(a);
+  else
+    stage2d_strip_kernel<double, kEuler, H><<<grid, block, 0, s>>>(a);
   return hipGetLastError();
 }
 

@@ -140,6 +140,13 @@ hipError_t launch_init(const npw_solver* s, hipStream_t st) {
 // A 1D single grid launched with at most 128 threads per workgroup over at most kPackMax tiles
 // exchanges alpha through its packed slots (see StageArgs::pack); the block size and so the tile
 // count are fixed between state checks, which clear those slots.
+// The scheme every instance of the solver uses, when a kernel is built for it alone.
+int one_scheme(const npw_solver* s) {
+  for (const InstDev& h : s->h_inst)
+    if (h.recon != NPW_RBF_WENO5 || h.sw != NPW_SWITCH_MONOTONE) return npw::kSchemeAny;
+  return npw::kSchemeRbfWeno5Switch;
+}
+
 bool use_pack(const npw_solver* s) { return s->pack != nullptr && s->block <= 128 && s->ntiles <= npw::kPackMax; }
 
 StageArgs stage_args(const npw_solver* s, int stage, int par, void* out) {
@@ -161,6 +168,7 @@ StageArgs stage_args(const npw_solver* s, int stage, int par, void* out) {
   a.any_k2 = s->any_k2;
   a.spread = s->spread;
   a.pack = use_pack(s) ? s->pack : nullptr;
+  a.scheme = one_scheme(s);
   return a;
 }
 

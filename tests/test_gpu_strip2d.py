@@ -65,6 +65,21 @@ def test_strip_shapes_fp64(shape, recon, monkeypatch):
     assert (ls["tile_x"], ls["tile_y"], ls["lds_shared"]) == (62, _H[shape], 0)
 
 
+@pytest.mark.parametrize("shape", [6, 8])
+def test_strip_rbf_weno5_without_the_switch_fp64(shape, monkeypatch):
+    """RBF-WENO5 with the switch on runs a strip kernel built for that scheme alone; with the
+    switch off it runs the strip that reads the scheme from the record.  Both bit for bit."""
+    _say(f"strip rbf_weno5 switch off shape={shape}")
+    monkeypatch.setenv("NPW_TILE2D", str(shape))
+    nx, ny = 131, 150  # smooth periodic data: without the switch the quadrants' jumps oscillate
+    x = I.cell_centers(nx, 0.0, 1.0)[None, :]
+    y = I.cell_centers(ny, 0.0, 1.0)[:, None]
+    rho = 1.0 + 0.3 * np.sin(2 * np.pi * x) * np.cos(2 * np.pi * y)
+    U = I.euler_prim_to_cons(rho, 0.4 + 0 * rho, 1.0 + 0.2 * np.cos(2 * np.pi * x) + 0 * rho, v=-0.3 + 0 * rho)
+    w = _quadrants(nx, ny, I.PERIODIC).with_(u0=U.reshape(-1), switch_mode=I.SWITCH_OFF)
+    _check_fp64(w, 3)
+
+
 @pytest.mark.parametrize("n,ny,bc", [(5, 3, I.PERIODIC), (62, 32, I.TRANSMISSIVE), (63, 33, I.PERIODIC),
                                      (124, 65, I.TRANSMISSIVE), (1, 7, I.PERIODIC), (9, 1, I.TRANSMISSIVE),
                                      (1, 1, I.PERIODIC), (2, 2, I.TRANSMISSIVE), (70, 4, I.PERIODIC),
