@@ -68,10 +68,12 @@ namespace {
 // Steps per captured graph (3 stage kernels each).  The host reads the instance table back after
 // every graph, which leaves the device idle for ~40 us; a single grid amortises that over 1024
 // steps once at least 8 such graphs remain (instantiating a 3072-node graph costs milliseconds,
-// which a short solve would not earn back), while a batch keeps 256 so that its tile table drops
-// finished instances sooner.
+// which a short solve would not earn back), while a batch keeps 64 so that its tile table drops
+// finished instances sooner (4096 Euler Riemann problems to T: 0.567 s with 256, 0.553 s with 64,
+// 0.565 s with 16, whose extra graph captures and host round trips cost more than they save).
 constexpr int kMaxGraphStepsSingle = 1024;
-constexpr int kMaxGraphStepsBatch = 256;
+constexpr int kMaxGraphStepsSingleTail = 256;  // a single grid's graphs once fewer than 8 x 1024 steps remain
+constexpr int kMaxGraphStepsBatch = 64;
 
 #define HIP_TRY(expr)                          \
   do {                                         \
@@ -859,7 +861,7 @@ static int run_steps(npw_solver* s, const double* T, int64_t max_steps, int64_t*
       rc = set_tiles(s, active, launched == 0);
       if (rc) return rc;
     }
-    const int cap = (max_k > kMaxGraphStepsBatch && est < 8.0 * max_k) ? kMaxGraphStepsBatch : max_k;
+    const int cap = (!s->batch && est < 8.0 * max_k) ? kMaxGraphStepsSingleTail : max_k;
     int want = est < 1.0 ? 1 : (int)std::min((double)cap, std::ceil(est));
     if (max_steps >= 0) want = (int)std::min<int64_t>(want, max_steps - progress);
     int k = 1;
