@@ -1070,6 +1070,9 @@ int rhs_noalloc_impl(const npw_params* p, const void* u, void* L_out, void* hip_
   a.any_k2 = p->recon >= NPW_RBF_WENO3 ? 1 : 0;
   a.spread = spread;
   a.pack = nullptr;  // the spread entries: the scratch array holds no packed slots
+  // the same kernel as a solver of these parameters (the 2D strip has a build for one scheme)
+  a.scheme = p->recon == NPW_RBF_WENO5 && p->switch_mode == NPW_SWITCH_MONOTONE ? npw::kSchemeRbfWeno5Switch
+                                                                               : npw::kSchemeAny;
   if (p->dim == 1) {
     const int block = env_block();
     a.ntiles = (int)((p->nx + block - 3) / (block - 2));

@@ -65,6 +65,17 @@ def test_noalloc_rhs_equals_solver_rhs_twice(name, first, second, prec, monkeypa
     _one(second(), prec)
 
 
+@pytest.mark.parametrize("scheme", [I.SWITCH_MONOTONE, I.SWITCH_OFF])
+def test_noalloc_on_the_strip_shape_equals_solver_fp32(scheme, monkeypatch):
+    """With the 62 x 16 column strip asked for, both entry points run the same strip kernel: the
+    one built for RBF-WENO5 with the switch, or the one that reads the scheme from the record."""
+    monkeypatch.setenv("NPW_BLOCK", "128")
+    monkeypatch.setenv("NPW_TILE2D", "6")
+    _say(f"noalloc strip switch={scheme}")
+    _one(_euler2d(300, 170).with_(switch_mode=scheme), B.FP32)
+    _one(_euler2d(70, 13).with_(switch_mode=scheme), B.FP32)
+
+
 def test_noalloc_reports_a_bad_state_and_leaves_the_output():
     import torch
     _say("noalloc status of a non-finite state")
