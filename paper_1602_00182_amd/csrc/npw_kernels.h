@@ -271,8 +271,8 @@ __device__ __forceinline__ void stage1d_tile(const StageArgs& a, const Tile tile
       }
     }
   }
-  // alpha of the stage input (max over the spread entries: the whole wave takes part), then the
-  // step size of a first stage, which its lead thread records for the two stages that follow
+  // alpha of the stage input (max over the packed or spread entries: the whole wave takes part),
+  // then the step size of a first stage, which its lead thread records for the two that follow
   unsigned long long alpha_bits;
   if constexpr (PACK) {
     alpha_bits = double_to_bits(double(pack_max<R, kPackLoads<R>>(pv)));

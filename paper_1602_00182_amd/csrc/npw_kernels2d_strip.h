@@ -28,10 +28,10 @@ constexpr int kStripTX = 62;  // owned columns of a strip (cells -1..62 of a row
 constexpr int kStripCH = 4;   // rows per chunk (one per wave in the x sweep and the update)
 
 // H = rows of a strip (a multiple of kStripCH).  Euler, four components, k = 3 component-wise.
-// Float: 6 waves per SIMD, the most its 24 KB of LDS allows; it needs 77 vector registers because
-// nothing is held across the chunk loop but the march's previous-cell flag and weight denominators,
-// the running spectral radii and the lane index (made opaque each chunk), and the next chunk's
-// rows travel from memory to LDS without registers.
+// Float: 6 waves per SIMD, the most its 24 KB of LDS allows; it needs 77 vector registers (71 when
+// built for one scheme) because nothing is held across the chunk loop but the march's previous-cell
+// flag and weight denominators, the running spectral radii and the lane index (made opaque each
+// chunk), and the next chunk's rows travel from memory to LDS without registers.
 // SCHEME: kSchemeAny reads the reconstruction from the instance record; kSchemeRbfWeno5Switch is
 // built for RBF-WENO5 with the switch alone (every instance of the launch uses it), so that the
 // compiler sees no other scheme's code or run-time choice (118.3 -> 112.8 us per 2048^2 stage).
