@@ -218,7 +218,7 @@ int npweno_launch_shape(const npw_solver* s, int32_t* block_1d, int32_t* tile_x,
  * bit-identical to solving it alone with npweno_create/npweno_solve in the same precision.
  * Requests never fail one another: a request that becomes non-finite or non-physical is
  * retired with its error and last good state. */
-/* The pools step with workgroups of 256 threads (NPW_BLOCK = 64, 128, 256 or 512 overrides).
+/* The pools step with workgroups of 512 threads (NPW_BLOCK = 64, 128, 256 or 512 overrides).
  * max_slots in [1, 65536]; precision NPW_FP32 or NPW_FP64 for every request; hbm_budget_bytes at
  * least 3 * 256 elements.  hip_stream is not used: requests enter and leave as host copies, and the
  * server works on private streams of its own (pass NULL). */

@@ -67,9 +67,10 @@ struct Pool {
 };
 
 // Stage workgroup size of the pools (tile = block - 2 cells); NPW_BLOCK overrides.  Measured on the
-// 2000-request trace (64 MiB arena): 2.89e10 cell-updates/s at 256 against 1.92e10 at 128 and 1.06e10
-// at 64, so the pools keep 256 even though single batches tune to smaller blocks.
-constexpr int kDefaultBlock = 256;
+// 2000-request trace (64 MiB arena): 4.58e10-4.60e10 cell-updates/s at 512 against 3.41e10-3.47e10 at
+// 256 and 2.18e10-2.20e10 at 128 (earlier kernels: 2.89e10 at 256, 1.92e10 at 128, 1.06e10 at 64),
+// so the pools take the largest tiles even though single batches tune to smaller blocks.
+constexpr int kDefaultBlock = 512;
 
 int server_block() {
   const char* e = std::getenv("NPW_BLOCK");
