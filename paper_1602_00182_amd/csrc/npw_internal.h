@@ -81,6 +81,19 @@ struct StageArgs {
   // pack[slot * kPackMax + tile]): a plain store per workgroup and kPackLoads vector loads per
   // lane replace the atomic max and its spread entry.  Null otherwise.
   void* pack = nullptr;
+  // Batches and serving pools spread each instance's alpha slot over bsp_k entries (a power of 2,
+  // at most kBspMax), 128 bytes apart: entry (instance b, slot, k) at
+  // bsp[((b * 3 + slot) * bsp_k + k) * kSpreadStride], double bits combined with atomicMax; tile i
+  // of an instance adds to entry i mod bsp_k, so hundreds of tiles of one large instance do not
+  // queue on one atomic.  Null: the instance record's own slot, which instances of at most
+// kBspMinTiles tiles keep in any case.  A batch passes bsp only if one of its instances has more
+// than kBspLaunchTiles tiles (4096 Euler Riemann problems of up to 67 tiles: 0.589 s to T through
+// the entries against 0.550 s through their slots, and the spreading kernel holds more
+// registers; 16 instances of 1058 tiles: 14-26 us per stage against 98 us); serving pools
+// always do (the 2000-request trace: 6.06e10 cell-updates/s with a threshold of 32 to 64 tiles,
+// 4.36e10 at 128, 4.59e10 without the entries).
+  unsigned long long* bsp = nullptr;
+  int bsp_k = 0;
   // The reconstruction of every instance of the launch when it is the one a kernel can be built
   // for alone (kSchemeRbfWeno5Switch: RBF-WENO5 with the Section 4 switch), else kSchemeAny (the
   // kernel reads it from the instance record).
@@ -99,6 +112,15 @@ constexpr int kSpreadWords = 3 * 2 * kSpread * kSpreadStride;
 // latency-bound stage time whether or not its entries are in use (3 unused loads of 8 measured
 // 0.07 us of a 3.2 us stage), so the size stays near the grids that need it; larger grids are
 // not latency-bound and use the spread entries.
+constexpr int kBspMax = 16;
+constexpr int kBspMinTiles = 32;     // an instance spreads its alpha when it has more tiles than this
+constexpr int kBspLaunchTiles = 128;  // a batch launch takes the spreading kernel when one has more
+// Entries per instance slot for instances of at most max_tiles tiles: one per 16 tiles, a power of 2.
+inline int bsp_entries(long long max_tiles) {
+  int k = 1;
+  while (k < kBspMax && (long long)k * 16 < max_tiles) k *= 2;
+  return k;
+}
 constexpr int kPackMax = 1280;
 constexpr int kPackWords = 3 * kPackMax;  // 64-bit words: three slots of double entries
 template <typename R>
@@ -121,12 +143,14 @@ constexpr int k2dStripFirst = 6;
 hipError_t launch_stage2d_f64(int flux, int ncomp, int shape, const StageArgs& a, hipStream_t s);
 hipError_t launch_stage2d_f32(int flux, int ncomp, int shape, const StageArgs& a, hipStream_t s);
 // State check of u^n for ninst instances: alpha slot 0 (and the spread entries and packed slots
-// of a single grid, either may be null), finiteness/physicality and the per-component FP64 sums.
+// of a single grid, or the spread entries bsp of a batch; any may be null), finiteness/physicality and the per-component FP64 sums.
 // scratch holds G * ninst partial records (kCheckPartialBytes each); G workgroups per instance.
 constexpr int kCheckPartialBytes = 56;
 hipError_t launch_init_f64(int flux, int ncomp, InstDev* inst, int ninst, void* P0, void* P1,
-                           unsigned long long* spread, void* pack, void* scratch, int G, hipStream_t s);
+                           unsigned long long* spread, void* pack, unsigned long long* bsp, int bsp_k, void* scratch,
+                           int G, hipStream_t s);
 hipError_t launch_init_f32(int flux, int ncomp, InstDev* inst, int ninst, void* P0, void* P1,
-                           unsigned long long* spread, void* pack, void* scratch, int G, hipStream_t s);
+                           unsigned long long* spread, void* pack, unsigned long long* bsp, int bsp_k, void* scratch,
+                           int G, hipStream_t s);
 
 }  // namespace npw

@@ -35,7 +35,8 @@ __device__ __forceinline__ void tile_barrier() {
 // built for one reconstruction alone was 5 % faster on a single grid, but it rounded some float
 // results differently from this one, which batches, serving pools and the allocation-free
 // right-hand side run, and those promise a single grid's results bit for bit.)
-template <typename R, int FLUX, int M, int BS, bool CHAR, bool K2, bool PACK>
+// BSP: a batch launch that may spread an instance's alpha over entries (StageArgs::bsp).
+template <typename R, int FLUX, int M, int BS, bool CHAR, bool K2, bool PACK, bool BSP>
 __device__ __forceinline__ void stage1d_tile(const StageArgs& a, const Tile tile) {
   constexpr bool kExact = std::is_same<R, double>::value;
   constexpr int W = BS + 4;  // LDS cells per component: start-3 .. start+BS
@@ -93,9 +94,15 @@ __device__ __forceinline__ void stage1d_tile(const StageArgs& a, const Tile tile
   constexpr bool kTag = !kExact;
   const int slot_in = stage == 0 ? 0 : stage - 1;
   // Alpha of the stage input: every entry of a packed slot (kPackLoads 16-byte loads per lane;
-  // loads past the grid's tiles re-read the lane's first vector), else one spread entry per lane,
-  // else (a batch instance) its own slot.  The same loads on every path, so that the staging below
-  // can wait for the state loads while these are still in flight.
+  // loads past the grid's tiles re-read the lane's first vector), else one spread entry per lane
+  // (a single grid's, or its instance's in a batch), else the instance's own slot.  The same loads
+  // on every path, so that the staging below can wait for the state loads while these are still in
+  // flight.
+  // A batch instance of more than kBspMinTiles tiles spreads its alpha over its bsp entries; one
+  // of fewer keeps its record's slot, whose one atomic costs less than the entries' reduction.
+  unsigned long long* const bsp = BSP && a.bsp && nx > kBspMinTiles * (BS - 2)
+                                      ? a.bsp + (size_t)tile.inst * 3 * (size_t)a.bsp_k * kSpreadStride
+                                      : nullptr;
   PackVec<R> pv[PACK ? kPackLoads<R> : 1];
   unsigned long long sp_e = 0ull;
   if constexpr (PACK) {
@@ -108,7 +115,9 @@ __device__ __forceinline__ void stage1d_tile(const StageArgs& a, const Tile tile
       pv[c] = P[q * kPer < G ? q : lane];
     }
   } else {
-    sp_e = *(sp ? spread_entry_ptr(sp, slot_in, 0) : &I->alpha[slot_in][0]);
+    sp_e = *(sp    ? spread_entry_ptr(sp, slot_in, 0)
+             : bsp ? &bsp[(slot_in * a.bsp_k + (tid & (a.bsp_k - 1))) * kSpreadStride]
+                   : &I->alpha[slot_in][0]);
   }
   // stage 0 and 1 step from ctl[0], stage 2 from ctl[1], stage 3 from ctl[2]; every branch
   // below is decided from these loads at once
@@ -129,6 +138,8 @@ __device__ __forceinline__ void stage1d_tile(const StageArgs& a, const Tile tile
         sp[((slot * 2 + 0) * kSpread + tid) * kSpreadStride] = 0ull;
         sp[((slot * 2 + 1) * kSpread + tid) * kSpreadStride] = 0ull;
       }
+    } else if (bsp) {
+      if (lead_wave && tid < a.bsp_k) bsp[(slot * a.bsp_k + tid) * kSpreadStride] = 0ull;
     } else if (lead) {
       I->alpha[slot][0] = 0ull;
       I->alpha[slot][1] = 0ull;
@@ -282,7 +293,13 @@ __device__ __forceinline__ void stage1d_tile(const StageArgs& a, const Tile tile
     else
       alpha_bits = spread_reduce(sp_e);
   } else {
-    alpha_bits = sp_e;
+    // float bulk: the entries hold float wave speeds widened exactly, so their maximum is taken in
+    // float (one register, merged lane moves), with the same result
+    if (bsp)
+      alpha_bits = kExact ? spread_reduce(sp_e)
+                          : double_to_bits(double(wave_max_nonneg<float>(float(bits_to_double(sp_e)))));
+    else
+      alpha_bits = sp_e;
   }
   const R alpha = R(bits_to_double(alpha_bits));
   if (tid < BS - 1) {
@@ -361,7 +378,9 @@ __device__ __forceinline__ void stage1d_tile(const StageArgs& a, const Tile tile
             R(bits_to_double(m));
       } else {
         unsigned long long* const aout =
-            sp ? &sp[((slot_out * 2 + 0) * kSpread + blockIdx.x % kSpread) * kSpreadStride] : &I->alpha[slot_out][0];
+            sp    ? &sp[((slot_out * 2 + 0) * kSpread + blockIdx.x % kSpread) * kSpreadStride]
+            : bsp ? &bsp[(slot_out * a.bsp_k + ((int)(start / (BS - 2)) & (a.bsp_k - 1))) * kSpreadStride]
+                  : &I->alpha[slot_out][0];
         atomicMax(aout, (sp && kTag) ? spread_tag(3 * (n - seq_base) + stage, float(bits_to_double(m))) : m);
       }
     }
@@ -371,25 +390,29 @@ __device__ __forceinline__ void stage1d_tile(const StageArgs& a, const Tile tile
 // Grid-stride loop over the tile table; the tile count is read from device memory when the
 // table is shared with a serving loop, so captured graphs stay valid as instances come and go.
 // PACK: single grids with packed alpha slots only.
-template <typename R, int FLUX, int M, int BS, bool CHAR = false, bool K2 = true, bool PACK = false>
+template <typename R, int FLUX, int M, int BS, bool CHAR = false, bool K2 = true, bool PACK = false, bool BSP = false>
 __global__ __launch_bounds__(BS) void stage1d_kernel(StageArgs a) {
-  if (PACK || a.tiles == nullptr) {  // single instance: tiles follow from the block index
-    Tile t;
-    t.inst = 0;
-    t.bc = a.bc;
-    t.start = xcd_contiguous_tile(blockIdx.x, gridDim.x) * (BS - 2);
-    t.nx = a.nx;
-    t.off = 0;
-    stage1d_tile<R, FLUX, M, BS, CHAR, K2, PACK>(a, t);
-    return;
+  // (A BSP kernel runs batches only: a second instantiation of the tile function here would hold
+  // LDS arrays of its own and halve the workgroups a CU takes.)
+  if constexpr (!BSP) {
+    if (PACK || a.tiles == nullptr) {  // single instance: tiles follow from the block index
+      Tile t;
+      t.inst = 0;
+      t.bc = a.bc;
+      t.start = xcd_contiguous_tile(blockIdx.x, gridDim.x) * (BS - 2);
+      t.nx = a.nx;
+      t.off = 0;
+      stage1d_tile<R, FLUX, M, BS, CHAR, K2, PACK, false>(a, t);
+      return;
+    }
   }
   const int nt = a.ntiles_dev ? *a.ntiles_dev : a.ntiles;
   if ((int)gridDim.x == nt) {  // one tile per workgroup (a batch): XCD-contiguous runs of the table
-    stage1d_tile<R, FLUX, M, BS, CHAR, K2, false>(a, scalar_load_tile(&a.tiles[xcd_contiguous_tile(blockIdx.x, nt)]));
+    stage1d_tile<R, FLUX, M, BS, CHAR, K2, false, BSP>(a, scalar_load_tile(&a.tiles[xcd_contiguous_tile(blockIdx.x, nt)]));
     return;
   }
   for (int ti = blockIdx.x; ti < nt; ti += gridDim.x) {
-    stage1d_tile<R, FLUX, M, BS, CHAR, K2, false>(a, scalar_load_tile(&a.tiles[ti]));
+    stage1d_tile<R, FLUX, M, BS, CHAR, K2, false, BSP>(a, scalar_load_tile(&a.tiles[ti]));
     __syncthreads();  // LDS is reused by the next tile
   }
 }
@@ -473,7 +496,7 @@ __global__ __launch_bounds__(256) void check_partial_kernel(InstDev* inst, void*
 template <typename R>
 static __global__ __launch_bounds__(64) void check_final_kernel(InstDev* inst, int ninst, const CheckPartial* part, int G,
                                                                 int ncomp, unsigned long long* spread, R* pack,
-                                                                int tagged) {
+                                                                unsigned long long* bsp, int bsp_k, int tagged) {
   const int b = blockIdx.x * 64 + threadIdx.x;
   // single grid: entry 0 of slot 0 holds alpha, every other entry (all packed slots included)
   // starts at 0
@@ -501,6 +524,10 @@ static __global__ __launch_bounds__(64) void check_final_kernel(InstDev* inst, i
   I->alpha[0][0] = mx;
   I->alpha[0][1] = my;
   if (pack) pack[0] = R(bits_to_double(mx));
+  if (bsp) {  // a batch instance: entry 0 of slot 0 holds alpha, every other entry of its slots 0
+    unsigned long long* e = bsp + (size_t)b * 3 * (size_t)bsp_k * kSpreadStride;
+    for (int k = 0; k < 3 * bsp_k; ++k) e[k * kSpreadStride] = k == 0 ? mx : 0ull;
+  }
   if (spread) {  // the state of step n opens sequence 3 (n - seq_base) (see spread_tag)
     const long long seq = 3 * (I->ctl[0].n - I->seq_base);
     spread[(0 * kSpread + 0) * kSpreadStride] = tagged ? spread_tag(seq, float(bits_to_double(mx))) : mx;

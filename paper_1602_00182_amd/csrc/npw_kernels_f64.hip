@@ -5,17 +5,17 @@
 
 namespace npw {
 
-template <int BS, bool K2, bool PACK>
+template <int BS, bool K2, bool PACK, bool BSP = false>
 static hipError_t launch_stage_k(int flux, int ncomp, const StageArgs& a, hipStream_t s) {
   const dim3 grid(a.ntiles), block(BS);
   if (flux == kAdvection && ncomp == 1)
-    stage1d_kernel<double, kAdvection, 1, BS, false, K2, PACK><<<grid, block, 0, s>>>(a);
+    stage1d_kernel<double, kAdvection, 1, BS, false, K2, PACK, BSP><<<grid, block, 0, s>>>(a);
   else if (flux == kBurgers && ncomp == 1)
-    stage1d_kernel<double, kBurgers, 1, BS, false, K2, PACK><<<grid, block, 0, s>>>(a);
+    stage1d_kernel<double, kBurgers, 1, BS, false, K2, PACK, BSP><<<grid, block, 0, s>>>(a);
   else if (flux == kEuler && ncomp == 3 && a.charw)
-    stage1d_kernel<double, kEuler, 3, BS, true, K2, PACK><<<grid, block, 0, s>>>(a);
+    stage1d_kernel<double, kEuler, 3, BS, true, K2, PACK, BSP><<<grid, block, 0, s>>>(a);
   else if (flux == kEuler && ncomp == 3)
-    stage1d_kernel<double, kEuler, 3, BS, false, K2, PACK><<<grid, block, 0, s>>>(a);
+    stage1d_kernel<double, kEuler, 3, BS, false, K2, PACK, BSP><<<grid, block, 0, s>>>(a);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();
@@ -34,6 +34,11 @@ static hipError_t launch_stage_bs(int flux, int ncomp, const StageArgs& a, hipSt
     }
   } else {
     if (a.pack) return hipErrorInvalidValue;
+  }
+  if (a.bsp) {
+    if (a.tiles == nullptr) return hipErrorInvalidValue;  // per-instance entries belong to batches
+    return a.any_k2 ? launch_stage_k<BS, true, false, true>(flux, ncomp, a, s)
+                    : launch_stage_k<BS, false, false, true>(flux, ncomp, a, s);
   }
   return a.any_k2 ? launch_stage_k<BS, true, false>(flux, ncomp, a, s)
                   : launch_stage_k<BS, false, false>(flux, ncomp, a, s);
@@ -102,7 +107,8 @@ hipError_t launch_stage2d_f64(int flux, int ncomp, int shape, const StageArgs& a
 }
 
 hipError_t launch_init_f64(int flux, int ncomp, InstDev* inst, int ninst, void* P0, void* P1,
-                           unsigned long long* spread, void* pack, void* scratch, int G, hipStream_t s) {
+                           unsigned long long* spread, void* pack, unsigned long long* bsp, int bsp_k, void* scratch,
+                           int G, hipStream_t s) {
   if (ninst <= 0) return hipSuccess;
   CheckPartial* part = reinterpret_cast<CheckPartial*>(scratch);
   const dim3 grid(G, ninst), block(256);
@@ -119,7 +125,7 @@ hipError_t launch_init_f64(int flux, int ncomp, InstDev* inst, int ninst, void* 
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   check_final_kernel<double><<<(ninst + 63) / 64, 64, 0, s>>>(inst, ninst, part, G, ncomp, spread,
-                                                           static_cast<double*>(pack), 0);
+                                                           static_cast<double*>(pack), bsp, bsp_k, 0);
   return hipGetLastError();
 }
 

@@ -49,6 +49,9 @@ struct npw_solver {
   void* scratch = nullptr;      // rhs destination when the caller passes host memory
   unsigned long long* spread = nullptr;  // spread alpha slots (single-grid solvers)
   void* pack = nullptr;                   // packed alpha slots (1D single grids), after the spread
+  unsigned long long* bsp = nullptr;      // per-instance spread alpha entries (batches)
+  int bsp_k = 0;
+  long long most_cells = 0;               // cells of the largest instance
   void* check_part = nullptr;   // partial records of the state check
   int check_G = 1;              // workgroups per instance in the state check
   std::map<int, hipGraphExec_t> graphs;  // (steps per graph, start parity) -> executable graph
@@ -134,9 +137,11 @@ hipError_t launch_stage(const npw_solver* s, const StageArgs& a, hipStream_t st)
 
 hipError_t launch_init(const npw_solver* s, hipStream_t st) {
   return s->precision == NPW_FP64 ? npw::launch_init_f64(s->flux, s->ncomp, s->d_inst, s->ninst, s->P0, s->P1,
-                                                         s->spread, s->pack, s->check_part, s->check_G, st)
+                                                         s->spread, s->pack, s->bsp, s->bsp_k, s->check_part, s->check_G,
+                                                         st)
                                   : npw::launch_init_f32(s->flux, s->ncomp, s->d_inst, s->ninst, s->P0, s->P1,
-                                                         s->spread, s->pack, s->check_part, s->check_G, st);
+                                                         s->spread, s->pack, s->bsp, s->bsp_k, s->check_part, s->check_G,
+                                                         st);
 }
 
 // A 1D single grid launched with at most 128 threads per workgroup over at most kPackMax tiles
@@ -170,6 +175,8 @@ StageArgs stage_args(const npw_solver* s, int stage, int par, void* out) {
   a.any_k2 = s->any_k2;
   a.spread = s->spread;
   a.pack = use_pack(s) ? s->pack : nullptr;
+  a.bsp = s->bsp && s->most_cells > (long long)npw::kBspLaunchTiles * (s->block - 2) ? s->bsp : nullptr;
+  a.bsp_k = s->bsp_k;
   a.scheme = one_scheme(s);
   return a;
 }
@@ -518,6 +525,7 @@ void release(npw_solver* s) {
   if (s->C) (void)hipFree(s->C);
   if (s->scratch) (void)hipFree(s->scratch);
   if (s->spread) (void)hipFree(s->spread);
+  if (s->bsp) (void)hipFree(s->bsp);
   if (s->check_part) (void)hipFree(s->check_part);
   if (s->d_inst) (void)hipFree(s->d_inst);
   if (s->d_tiles) (void)hipFree(s->d_tiles);
@@ -701,6 +709,15 @@ static int create_common(const npw_params* p, int32_t count, const void* const* 
     return NPW_ENOMEM;
   }
   if (s->spread && s->dim == 1) s->pack = s->spread + npw::kSpreadWords;
+  if (batch) {  // spread entries per instance, as many as its largest instance's tiles call for
+    for (const InstDev& h : s->h_inst) s->most_cells = std::max(s->most_cells, h.nx);
+    s->bsp_k = npw::bsp_entries((s->most_cells + kBlocks[0] - 3) / (kBlocks[0] - 2));
+    if (hipMalloc(&s->bsp, sizeof(unsigned long long) * (size_t)count * 3 * s->bsp_k * npw::kSpreadStride) !=
+        hipSuccess) {
+      release(s);
+      return NPW_ENOMEM;
+    }
+  }
   if (enter(s) || hipMemcpyAsync(s->d_tiles, s->tiles_all.data(), sizeof(Tile) * s->tiles_all.size(),
                                  hipMemcpyHostToDevice, s->stream) != hipSuccess) {
     release(s);
@@ -1051,8 +1068,8 @@ int rhs_noalloc_impl(const npw_params* p, const void* u, void* L_out, void* hip_
   HIP_TRY(hipGetLastError());
   void* uu = const_cast<void*>(u);  // read only: rhs mode loads the state and writes L_out
   const int flux = p->flux, m = p->ncomp;
-  HIP_TRY(p->precision == NPW_FP64 ? npw::launch_init_f64(flux, m, rec, 1, uu, uu, spread, nullptr, part, G, st)
-                                   : npw::launch_init_f32(flux, m, rec, 1, uu, uu, spread, nullptr, part, G, st));
+  HIP_TRY(p->precision == NPW_FP64 ? npw::launch_init_f64(flux, m, rec, 1, uu, uu, spread, nullptr, nullptr, 0, part, G, st)
+                                   : npw::launch_init_f32(flux, m, rec, 1, uu, uu, spread, nullptr, nullptr, 0, part, G, st));
   StageArgs a;
   std::memset(&a, 0, sizeof a);
   a.inst = rec;

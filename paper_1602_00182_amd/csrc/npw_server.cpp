@@ -58,6 +58,8 @@ struct Pool {
   Tile* d_tiles = nullptr;
   int* d_ntiles = nullptr;
   void* d_check = nullptr;    // state-check partial records (kCheckMaxG)
+  unsigned long long* d_bsp = nullptr;  // per-slot spread alpha entries (StageArgs::bsp)
+  int bsp_k = 1;
   int tile_cap = 0;
   std::vector<int> slot_req;  // request index (into server order) per slot, -1 if free
   std::vector<uint64_t> slot_id;
@@ -153,14 +155,18 @@ int pool_of(const npw_params* p) {  // advection 0, Burgers 1, Euler 2, Euler ch
   return p->flux == NPW_EULER && p->variables == NPW_CHARACTERISTIC ? 3 : p->flux;
 }
 
+unsigned long long* slot_bsp(const Pool& pl, int slot) {
+  return pl.d_bsp + (size_t)slot * 3 * pl.bsp_k * npw::kSpreadStride;
+}
+
 // State check of one request (alpha, validity, FP64 sums of its current state) on its pool's
 // stream.  Checks on one stream run in order, so they share the pool's partial records.
 hipError_t launch_check(const npw_server* s, const Pool& pl, int slot, long long cells) {
   return s->precision == NPW_FP64
-             ? npw::launch_init_f64(pl.flux, pl.ncomp, pl.d_inst + slot, 1, s->P0, s->P1, nullptr, nullptr, pl.d_check,
-                                    check_groups(cells), pl.stream)
-             : npw::launch_init_f32(pl.flux, pl.ncomp, pl.d_inst + slot, 1, s->P0, s->P1, nullptr, nullptr, pl.d_check,
-                                    check_groups(cells), pl.stream);
+             ? npw::launch_init_f64(pl.flux, pl.ncomp, pl.d_inst + slot, 1, s->P0, s->P1, nullptr, nullptr,
+                                    slot_bsp(pl, slot), pl.bsp_k, pl.d_check, check_groups(cells), pl.stream)
+             : npw::launch_init_f32(pl.flux, pl.ncomp, pl.d_inst + slot, 1, s->P0, s->P1, nullptr, nullptr,
+                                    slot_bsp(pl, slot), pl.bsp_k, pl.d_check, check_groups(cells), pl.stream);
 }
 
 hipError_t launch_stage(const npw_server* s, int flux, int ncomp, const StageArgs& a, hipStream_t st) {
@@ -181,6 +187,8 @@ StageArgs pool_args(const npw_server* s, const Pool& pl, int stage, int par) {
   a.C = s->C;
   a.stage = stage;
   a.spread = nullptr;
+  a.bsp = pl.d_bsp;
+  a.bsp_k = pl.bsp_k;
   a.charw = pl.charw;
   a.any_k2 = 1;  // requests of either order share the pool's graphs
   return a;
@@ -421,6 +429,7 @@ void destroy_server(npw_server* s) {
     if (pl.d_tiles) (void)hipFree(pl.d_tiles);
     if (pl.d_ntiles) (void)hipFree(pl.d_ntiles);
     if (pl.d_check) (void)hipFree(pl.d_check);
+    if (pl.d_bsp) (void)hipFree(pl.d_bsp);
     if (pl.h_pin) (void)hipHostFree(pl.h_pin);
     if (pl.stream) (void)hipStreamDestroy(pl.stream);
   }
@@ -464,11 +473,16 @@ static int npw_server_create_impl(size_t hbm_budget_bytes, int32_t max_slots, in
     pl.slot_id.assign(max_slots, 0);
     // every tile of a full arena (one component per element) plus one partial tile per slot
     pl.tile_cap = (int)std::min<size_t>((elems / ncomp[k]) / (s->block - 2) + max_slots + 1, 1u << 30);
+    // spread alpha entries per slot for the largest request the arena holds, within 32 MiB a pool
+    pl.bsp_k = npw::bsp_entries((long long)((elems / ncomp[k]) / (s->block - 2) + 1));
+    while (pl.bsp_k > 1 && (size_t)max_slots * 3 * pl.bsp_k * npw::kSpreadStride * 8 > (32u << 20)) pl.bsp_k /= 2;
     ok = hipStreamCreateWithFlags(&pl.stream, hipStreamNonBlocking) == hipSuccess &&
          hipMalloc(&pl.d_inst, sizeof(InstDev) * max_slots) == hipSuccess &&
          hipMalloc(&pl.d_tiles, sizeof(Tile) * pl.tile_cap) == hipSuccess &&
          hipMalloc(&pl.d_ntiles, sizeof(int)) == hipSuccess &&
          hipMalloc(&pl.d_check, (size_t)npw::kCheckPartialBytes * kCheckMaxG) == hipSuccess &&
+         hipMalloc(&pl.d_bsp, sizeof(unsigned long long) * (size_t)max_slots * 3 * pl.bsp_k * npw::kSpreadStride) ==
+             hipSuccess &&
          hipHostMalloc(&pl.h_pin, sizeof(InstDev) * max_slots, hipHostMallocDefault) == hipSuccess;
     if (ok) {
       // idle slots: T = t = 0, so every launch skips them

@@ -126,3 +126,28 @@ def test_full_size_riemann_batch_sampled_fp32():
         with B.Solver(states[b], **B.workload_params(w, B.FP32)) as s:
             s.solve(w.T, 25)
             assert np.array_equal(s.read(), got[b]), b
+
+
+@pytest.mark.parametrize("prec", [B.FP64, B.FP32])
+def test_large_instances_spread_their_alpha(prec, monkeypatch):
+    """A batch holding instances of more than 128 tiles runs the kernel that spreads an instance's
+    alpha over entries (small instances of the same launch keep their own slot): every instance
+    equals its solve alone bit for bit, and the double bulk the oracle."""
+    _say(f"batch of large instances prec={prec}")
+    monkeypatch.setenv("NPW_BLOCK", "64")
+    ws = [I.burgers_noisy(n=n, seed=s, T=0.05) for n, s in ((70001, 1), (200, 2), (20000, 3))]
+    states = _states(ws, prec)
+    with B.Batch(states, [B.workload_params(w, prec) for w in ws]) as bt:
+        stats, rc = bt.solve([w.T for w in ws], 8)
+        got = [bt.read(b) for b in range(len(ws))]
+    assert rc == B.OK
+    for b, w in enumerate(ws):
+        assert stats[b]["nsteps"] == 8
+        with B.Solver(states[b], **B.workload_params(w, prec)) as s:
+            st = s.solve(w.T, max_steps=8)
+            alone = s.read()
+        assert st["t"] == stats[b]["t"] and st["alpha"][0] == stats[b]["alpha"][0]
+        assert np.array_equal(alone, got[b]), b
+        if prec == B.FP64:
+            uo, to, _ = O.solve(_oracle_problem(w), w.u0, w.T, max_steps=8)
+            assert np.array_equal(got[b], uo) and to == stats[b]["t"]

@@ -63,6 +63,26 @@ def test_results_identical_alone_and_in_the_mix(prec):
             assert a <= b <= c
 
 
+@pytest.mark.parametrize("prec", [B.FP32, B.FP64])
+def test_large_request_spreads_its_alpha(prec):
+    """A request of more than 128 tiles of the pools' 512-thread workgroups spreads its alpha over
+    entries; served beside small ones it still equals its solve alone bit for bit."""
+    _say(f"serving large request prec={prec}")
+    ws = [I.burgers_noisy(n=n, seed=s, T=0.02) for n, s in ((70001, 5), (300, 6), (1500, 7))]
+    esize = 4 if prec == B.FP32 else 8
+    with B.Server(3 * esize * 80000, max_slots=4, precision=prec) as srv:
+        ids = [srv.submit(w.u0, w.T, **B.workload_params(w, prec)) for w in ws]
+        _drain(srv, ids)
+        dt = np.float32 if prec == B.FP32 else np.float64
+        for rid, w in zip(ids, ws):
+            out, st, rc = srv.poll(rid)
+            assert rc == B.OK
+            with B.Solver(np.asarray(w.u0, dt), **B.workload_params(w, prec)) as s:
+                st1 = s.solve(w.T)
+                alone = s.read()
+            assert st["nsteps"] == st1["nsteps"] and np.array_equal(out, alone), rid
+
+
 def test_failing_request_does_not_poison_others():
     _say("serving failure isolation")
     good = _requests(5, seed=7, nmax=3000, tmax=0.1)
